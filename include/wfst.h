@@ -1,0 +1,193 @@
+/*
+ * wfst.h -- C ABI of the MI355X (gfx950) library for Viterbi decoding and
+ * forward-backward over large sparse nondeterministic weighted finite-state
+ * transducers, after Argueta & Chiang, "Decoding with Finite-State Transducers
+ * on GPUs" (EACL 2017).
+ *
+ * Problem statement (paper, section 3): a WFST is (Q, Sigma, s, F, delta):
+ * states 0..num_states-1, input symbols 0..num_ilabels-1, one start state s,
+ * a final weight f[q] per state, and for every input symbol a a sparse
+ * |Q|x|Q| transition matrix delta[a].  There are no epsilon arcs.  The weight
+ * of an input string w_1..w_n is s^T (prod_t delta[w_t]) f (Eq. 1).
+ *
+ * Scores are log-domain FP32: arc_score = log p (higher is better; a cost
+ * c maps to score -c), final_score[q] = log f[q] with -inf for a non-final
+ * state.  Arcs are given as a flat list; the index of an arc in that list is
+ * its arc id.  Arc ids are what paths report, what breaks Viterbi ties (the
+ * lowest id wins) and what indexes posteriors and gradients.
+ *
+ * Viterbi evaluates Eq. 1 in the max-plus semiring with back-pointers (the
+ * pair semiring of section 3 on log scores; section 5.1 for the packed
+ * max and the on-device backtrace).  Forward-backward evaluates Eq. 1 in the
+ * log semiring (section 5.2) and returns log Z and the expected arc counts of
+ * Algorithm 2, which are also d(log Z)/d(arc_score).
+ *
+ * Conventions for every entry point
+ *   - Return value 0 = success; a negative value is a call-level error
+ *     (WFST_E*), with a message from wfst_last_error() on the calling thread.
+ *     No C++ exception crosses this ABI.
+ *   - Per-sentence outcomes go to a caller-owned status[] array (WFST_STATUS_*).
+ *   - "device" pointers are HIP device memory on the FST's device, written or
+ *     read asynchronously on `stream` (a hipStream_t; NULL = the null stream).
+ *     Results are valid once the stream has reached the end of the call.
+ *   - A batch is `batch` sentences: tokens[offsets[b] .. offsets[b+1]-1] is
+ *     sentence b; offsets has batch+1 entries, offsets[0] = 0, non-decreasing,
+ *     offsets[batch] = num_tokens (passed by value so that no device read is
+ *     needed to size work); num_tokens < 2^31.
+ */
+#ifndef WFST_H
+#define WFST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call-level return codes */
+#define WFST_OK 0
+#define WFST_EINVAL (-1)       /* bad argument (range, NaN/inf score, null pointer, ...) */
+#define WFST_ENOMEM (-2)       /* host or device allocation failed */
+#define WFST_EHIP (-3)         /* a HIP runtime call failed; message carries its string */
+#define WFST_EUNSUPPORTED (-4) /* size or option outside what this build supports */
+
+/* per-sentence status codes */
+#define WFST_STATUS_OK 0
+#define WFST_STATUS_NO_PATH 1   /* no accepting path: score / log Z = -inf */
+#define WFST_STATUS_BAD_TOKEN 2 /* a token outside [0, num_ilabels) */
+#define WFST_STATUS_BAD_INPUT 3 /* offsets not non-decreasing or inconsistent with num_tokens */
+
+typedef struct wfst_fst wfst_fst;   /* library-owned device layouts of one FST */
+typedef struct wfst_tape wfst_tape; /* library-owned forward pass state for a backward call */
+
+/* Optional creation parameters; pass NULL for defaults.  Zero fields mean "auto". */
+typedef struct wfst_options {
+    int32_t chunk_arcs;         /* arcs per lane chunk in the sliced layouts (1..64); 0 = auto */
+    int32_t threads_per_sentence; /* workgroup size per sentence (64,128,256,512,1024); 0 = auto */
+    int32_t checkpoint;         /* forward tape: -1/0 = auto, 1 = force sqrt(T) checkpointing, 2 = never */
+    int32_t reserved0;
+    int64_t tape_budget_bytes;  /* auto mode checkpoints when the full tape exceeds this; 0 = 8 GiB */
+    int64_t reserved1;
+} wfst_options;
+
+/* Layout statistics (for tuning and reporting). */
+typedef struct wfst_fst_info {
+    int32_t num_states, num_ilabels, start, chunk_arcs;
+    int64_t num_arcs;
+    int64_t fwd_elements, rev_elements;   /* padded arc slots in each sliced layout */
+    int64_t fwd_segments, rev_segments;   /* (label, dst) and (label, src) segments */
+    int64_t fwd_slices, rev_slices;
+    int32_t max_fwd_segments_per_label, max_rev_segments_per_label;
+    int32_t max_fwd_slots_per_label, max_rev_slots_per_label;
+    int64_t device_bytes;                 /* device memory held by the FST */
+} wfst_fst_info;
+
+/*
+ * Build the device layouts of an FST (paper, section 4 CSR/COO per symbol,
+ * reorganised per destination: see the layout notes in DESIGN).
+ *   src, dst, ilabel: host int32[num_arcs], ranges [0,num_states) / [0,num_ilabels).
+ *   olabel: host int32[num_arcs] or NULL (then best_olabels can not be asked for).
+ *   arc_score: host float[num_arcs], finite (NaN/inf -> WFST_EINVAL); -0 is
+ *     stored as +0.
+ *   final_score: host float[num_states], finite or -inf (NaN/+inf -> EINVAL).
+ *   start: the start state.  num_arcs < 2^31.
+ * The caller keeps ownership of its arrays (they may be freed on return).
+ * The library owns *out until wfst_fst_destroy.  Work is queued on `stream`
+ * and the call returns after the uploads finished.
+ */
+int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int64_t num_arcs,
+                    const int32_t *src, const int32_t *dst, const int32_t *ilabel,
+                    const int32_t *olabel, const float *arc_score, const float *final_score,
+                    const wfst_options *options, void *stream, wfst_fst **out);
+
+/* Replace the scores (training): arc_score_dev is a DEVICE float[num_arcs] in
+ * arc-id order, scattered into both layouts through the stored permutation;
+ * final_score_dev (nullable) a DEVICE float[num_states].  Values are not
+ * validated (a NaN propagates).  Asynchronous on stream. */
+int wfst_fst_set_scores(wfst_fst *fst, const float *arc_score_dev, const float *final_score_dev,
+                        void *stream);
+
+/* Free the FST's device memory (synchronises its device).  NULL-safe. */
+void wfst_fst_destroy(wfst_fst *fst);
+
+int wfst_fst_get_info(const wfst_fst *fst, wfst_fst_info *info);
+
+/*
+ * Viterbi decoding of a batch (paper, Algorithm 1 + section 5.1).
+ * Outputs (caller-owned DEVICE memory):
+ *   best_score float[batch]: FP32 score of the best accepting path, equal bit
+ *     for bit to a serial evaluation that adds one arc score at a time
+ *     (binary32, round to nearest even) and keeps the first of equal
+ *     candidates in arc-id order; -inf when there is no path.
+ *   best_arcs int32[num_tokens]: arc ids of that path, in input order
+ *     (-1 for a sentence without a path).  Ties: lowest arc id per state and
+ *     step, lowest state id among final states.
+ *   best_olabels int32[num_tokens] or NULL: olabel of each path arc.
+ *   status int32[batch].
+ * An empty sentence scores final_score[start] with an empty path.
+ */
+int wfst_viterbi(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                 const int32_t *tokens, float *best_score, int32_t *best_arcs,
+                 int32_t *best_olabels, int32_t *status, void *stream);
+
+/*
+ * Forward pass (paper, Algorithm 2 first loop, log semiring): log_z float[batch]
+ * (DEVICE), status int32[batch] (DEVICE).  *tape_out receives a library-owned
+ * record of the pass for wfst_backward; free it with wfst_tape_free.  The tape
+ * keeps pointers to offsets/tokens: they must stay valid and unchanged until
+ * the tape is freed.  log Z is the log of Eq. 1's value, -inf without a path.
+ */
+int wfst_forward(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                 const int32_t *tokens, float *log_z, int32_t *status, wfst_tape **tape_out,
+                 void *stream);
+
+/*
+ * Backward pass and expected counts (paper, Algorithm 2 second and last loops).
+ *   grad_log_z: DEVICE float[batch] g_b, or NULL for all ones.
+ *   grad_arc_score: DEVICE float[num_arcs], OVERWRITTEN with
+ *     sum_b g_b * E_b[number of uses of arc k] = d(sum_b g_b log Z_b)/d score_k.
+ *   grad_final: DEVICE float[num_states] or NULL, overwritten with
+ *     sum_b g_b * P_b(path ends in q).
+ * Sentences without a path (or with a bad token) contribute zero.  The sum
+ * over b and over visits is taken in a fixed order: results are bitwise
+ * reproducible for a given FST, batch and library configuration.
+ */
+int wfst_backward(const wfst_fst *fst, const wfst_tape *tape, const float *grad_log_z,
+                  float *grad_arc_score, float *grad_final, void *stream);
+
+void wfst_tape_free(wfst_tape *tape);
+
+/* forward + backward with g_b = 1: log_z float[batch], arc_posterior
+ * float[num_arcs] = sum_b E_b[count_k] (for batch = 1 each value is in [0, n]
+ * and they sum to n), final_posterior float[num_states] or NULL. DEVICE memory. */
+int wfst_forward_backward(const wfst_fst *fst, int32_t batch, int64_t num_tokens,
+                          const int32_t *offsets, const int32_t *tokens, float *log_z,
+                          float *arc_posterior, float *final_posterior, int32_t *status,
+                          void *stream);
+
+/* Message for the last nonzero return on this thread ("" if none). */
+const char *wfst_last_error(void);
+
+/*
+ * Host-only layout query for tests (no GPU needed).  Builds the forward
+ * (direction 0: grouped by label then destination) or reverse (direction 1:
+ * by label then source) sliced layout into caller-allocated host arrays.
+ * Call first with all output pointers NULL to get the sizes in *sizes:
+ *   sizes[0] = elements, sizes[1] = slices, sizes[2] = segments.
+ * elem_other int32[elements]: the other end state of each slot (num_states
+ *   for a padding slot); elem_arc int32[elements]: arc id (-1 padding);
+ * slice_info int32[4*slices] {base, height, width, label};
+ * seg_info int32[4*segments] {key state, first chunk, chunks, label};
+ * label_slice int32[num_ilabels+1], label_seg int32[num_ilabels+1].
+ */
+int wfst_layout_host(int32_t num_states, int32_t num_ilabels, int64_t num_arcs,
+                     const int32_t *src, const int32_t *dst, const int32_t *ilabel,
+                     int32_t direction, int32_t chunk_arcs, int64_t *sizes,
+                     int32_t *elem_other, int32_t *elem_arc, int32_t *slice_info,
+                     int32_t *seg_info, int32_t *label_slice, int32_t *label_seg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WFST_H */

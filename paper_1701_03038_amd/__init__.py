@@ -1,0 +1,332 @@
+"""wfsthip: Viterbi and forward-backward over large sparse WFSTs on MI355X.
+
+A thin ctypes binding over ``libwfsthip.so`` (C ABI in ``include/wfst.h``).
+This module only marshals arguments: every step of decoding, forward,
+backward and expected counts runs in the library's HIP kernels.  PyTorch is
+used for device memory and streams; all device tensors are on the FST's GPU
+and calls are queued on the current torch stream.
+
+The library is required: importing works without it (so that the build can
+import the package), but every call raises ``WfstError`` when the shared
+library is missing instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "WfstError", "Fst", "Tape", "viterbi", "forward", "backward", "forward_backward",
+    "LogPartition", "log_partition", "load_library", "layout_host", "library_path",
+    "STATUS_OK", "STATUS_NO_PATH", "STATUS_BAD_TOKEN", "STATUS_BAD_INPUT",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(HERE, "libwfsthip.so")
+
+STATUS_OK, STATUS_NO_PATH, STATUS_BAD_TOKEN, STATUS_BAD_INPUT = 0, 1, 2, 3
+WFST_EINVAL, WFST_ENOMEM, WFST_EHIP, WFST_EUNSUPPORTED = -1, -2, -3, -4
+
+_lib = None
+
+
+class WfstError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"wfsthip error {code}: {msg}")
+        self.code = code
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("chunk_arcs", ctypes.c_int32), ("threads_per_sentence", ctypes.c_int32),
+                ("checkpoint", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("tape_budget_bytes", ctypes.c_int64), ("reserved1", ctypes.c_int64)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("num_states", ctypes.c_int32), ("num_ilabels", ctypes.c_int32),
+                ("start", ctypes.c_int32), ("chunk_arcs", ctypes.c_int32),
+                ("num_arcs", ctypes.c_int64),
+                ("fwd_elements", ctypes.c_int64), ("rev_elements", ctypes.c_int64),
+                ("fwd_segments", ctypes.c_int64), ("rev_segments", ctypes.c_int64),
+                ("fwd_slices", ctypes.c_int64), ("rev_slices", ctypes.c_int64),
+                ("max_fwd_segments_per_label", ctypes.c_int32),
+                ("max_rev_segments_per_label", ctypes.c_int32),
+                ("max_fwd_slots_per_label", ctypes.c_int32),
+                ("max_rev_slots_per_label", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+EXPORTS = (
+    "wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_destroy", "wfst_fst_get_info",
+    "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
+    "wfst_forward_backward", "wfst_last_error", "wfst_layout_host",
+)
+
+
+def load_library(path: str | None = None):
+    """Load libwfsthip.so (raises WfstError if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or library_path
+    if not os.path.exists(p):
+        raise WfstError(WFST_EUNSUPPORTED, f"{p} is missing: build it with __graft_entry__.build() "
+                                           "or python -m paper_1701_03038_amd.build")
+    lib = ctypes.CDLL(p)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.wfst_fst_create.argtypes = [i32, i32, i32, i64, P, P, P, P, P, P, P, P, ctypes.POINTER(P)]
+    lib.wfst_fst_set_scores.argtypes = [P, P, P, P]
+    lib.wfst_fst_destroy.argtypes = [P]
+    lib.wfst_fst_destroy.restype = None
+    lib.wfst_fst_get_info.argtypes = [P, ctypes.POINTER(_Info)]
+    lib.wfst_viterbi.argtypes = [P, i32, i64, P, P, P, P, P, P, P]
+    lib.wfst_forward.argtypes = [P, i32, i64, P, P, P, P, ctypes.POINTER(P), P]
+    lib.wfst_backward.argtypes = [P, P, P, P, P, P]
+    lib.wfst_tape_free.argtypes = [P]
+    lib.wfst_tape_free.restype = None
+    lib.wfst_forward_backward.argtypes = [P, i32, i64, P, P, P, P, P, P, P]
+    lib.wfst_last_error.argtypes = []
+    lib.wfst_last_error.restype = ctypes.c_char_p
+    lib.wfst_layout_host.argtypes = [i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
+    for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_viterbi",
+                 "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host"):
+        getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise WfstError(rc, _lib.wfst_last_error().decode(errors="replace"))
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device=None):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def layout_host(num_states, num_ilabels, src, dst, ilabel, direction=0, chunk_arcs=16):
+    """Build one sliced layout on the host (no GPU) and return its arrays."""
+    lib = load_library()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    ilabel = np.ascontiguousarray(ilabel, np.int32)
+    sizes = np.zeros(3, np.int64)
+    args = (num_states, num_ilabels, src.shape[0], _np_ptr(src), _np_ptr(dst), _np_ptr(ilabel),
+            direction, chunk_arcs)
+    _check(lib.wfst_layout_host(*args, _np_ptr(sizes), None, None, None, None, None, None))
+    E, S, G = (int(x) for x in sizes)
+    out = dict(elem_other=np.empty(E, np.int32), elem_arc=np.empty(E, np.int32),
+               slice_info=np.empty((S, 4), np.int32), seg_info=np.empty((G, 4), np.int32),
+               label_slice=np.empty(num_ilabels + 1, np.int32),
+               label_seg=np.empty(num_ilabels + 1, np.int32))
+    _check(lib.wfst_layout_host(*args, _np_ptr(sizes), *(_np_ptr(out[k]) for k in (
+        "elem_other", "elem_arc", "slice_info", "seg_info", "label_slice", "label_seg"))))
+    return out
+
+
+class Fst:
+    """Device layouts of one WFST (library-owned; freed by close())."""
+
+    def __init__(self, num_states, num_ilabels, start, src, dst, ilabel, arc_score, final_score,
+                 olabel=None, chunk_arcs=0, threads_per_sentence=0):
+        import torch
+        lib = load_library()
+        self.num_states, self.num_ilabels, self.start = int(num_states), int(num_ilabels), int(start)
+        arrs = [np.ascontiguousarray(x, np.int32) for x in (src, dst, ilabel)]
+        ol = None if olabel is None else np.ascontiguousarray(olabel, np.int32)
+        sc = np.ascontiguousarray(arc_score, np.float32)
+        fin = np.ascontiguousarray(final_score, np.float32)
+        self.num_arcs = int(arrs[0].shape[0])
+        opt = _Options(chunk_arcs, threads_per_sentence, 0, 0, 0, 0)
+        self.device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        _check(lib.wfst_fst_create(self.num_states, self.num_ilabels, self.start, self.num_arcs,
+                                   *(_np_ptr(a) for a in arrs), _np_ptr(ol), _np_ptr(sc), _np_ptr(fin),
+                                   ctypes.byref(opt), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.has_olabels = ol is not None
+
+    @classmethod
+    def from_synth(cls, f, **kw):
+        return cls(f.num_states, f.num_ilabels, f.start, f.src, f.dst, f.ilabel, f.arc_score,
+                   f.final_score, olabel=f.olabel, **kw)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise WfstError(WFST_EINVAL, "FST is closed")
+        return self._h
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(_lib.wfst_fst_get_info(self.handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def set_scores(self, arc_score, final_score=None):
+        """New scores from device float32 tensors (arc-id order), async on the current stream."""
+        for t in (arc_score, final_score):
+            if t is not None and (not t.is_cuda or t.dtype.itemsize != 4 or not t.is_contiguous()):
+                raise WfstError(WFST_EINVAL, "scores must be contiguous float32 device tensors")
+        _check(_lib.wfst_fst_set_scores(self.handle, _dptr(arc_score), _dptr(final_score), _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.wfst_fst_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _batch(offsets, tokens):
+    """Device int32 offsets [B+1] and tokens [N] (marshalled from arrays or lists)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+
+    def as_dev(x):
+        if isinstance(x, torch.Tensor):
+            return x.to(device=dev, dtype=torch.int32).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(x, np.int32), device=dev)
+
+    off, tok = as_dev(offsets), as_dev(tokens)
+    B = int(off.shape[0]) - 1
+    N = int(tok.shape[0])
+    return off, tok, B, N
+
+
+def batch_from_sentences(sentences):
+    """(offsets, tokens) int32 arrays from a list of token sequences."""
+    lens = [len(s) for s in sentences]
+    off = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    tok = np.concatenate([np.asarray(s, np.int32) for s in sentences]) if sentences else np.zeros(0, np.int32)
+    return off.astype(np.int32), tok.astype(np.int32)
+
+
+def viterbi(fst: Fst, offsets, tokens, olabels: bool = False):
+    """Best path per sentence: (best_score f32[B], best_arcs i32[N], status i32[B][, olabels i32[N]])."""
+    import torch
+    off, tok, B, N = _batch(offsets, tokens)
+    dev = off.device
+    score = torch.empty(B, dtype=torch.float32, device=dev)
+    arcs = torch.empty(N, dtype=torch.int32, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    ol = torch.empty(N, dtype=torch.int32, device=dev) if olabels else None
+    _check(_lib.wfst_viterbi(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(score), _dptr(arcs),
+                             _dptr(ol), _dptr(status), _stream()))
+    return (score, arcs, status, ol) if olabels else (score, arcs, status)
+
+
+class Tape:
+    """Library-owned record of a forward pass (needed by backward)."""
+
+    def __init__(self, fst, h, keep):
+        self.fst, self._h, self._keep = fst, h, keep
+
+    def free(self):
+        if self._h is not None and _lib is not None:
+            _lib.wfst_tape_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def forward(fst: Fst, offsets, tokens):
+    """(log_z f32[B], status i32[B], Tape)."""
+    import torch
+    off, tok, B, N = _batch(offsets, tokens)
+    log_z = torch.empty(B, dtype=torch.float32, device=off.device)
+    status = torch.empty(B, dtype=torch.int32, device=off.device)
+    h = ctypes.c_void_p()
+    _check(_lib.wfst_forward(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(log_z), _dptr(status),
+                             ctypes.byref(h), _stream()))
+    return log_z, status, Tape(fst, h, (off, tok, status))
+
+
+def backward(fst: Fst, tape: Tape, grad_log_z=None):
+    """d(sum_b g_b log Z_b)/d arc_score as a float32 device tensor [num_arcs]."""
+    import torch
+    if tape._h is None:
+        raise WfstError(WFST_EINVAL, "tape already freed")
+    grad = torch.empty(fst.num_arcs, dtype=torch.float32, device=tape._keep[0].device)
+    g = None
+    if grad_log_z is not None:
+        g = grad_log_z.to(dtype=torch.float32).contiguous()
+    _check(_lib.wfst_backward(fst.handle, tape._h, _dptr(g), _dptr(grad), None, _stream()))
+    return grad
+
+
+def forward_backward(fst: Fst, offsets, tokens):
+    """(log_z f32[B], arc_posterior f32[num_arcs] summed over the batch, status i32[B])."""
+    import torch
+    off, tok, B, N = _batch(offsets, tokens)
+    log_z = torch.empty(B, dtype=torch.float32, device=off.device)
+    post = torch.empty(fst.num_arcs, dtype=torch.float32, device=off.device)
+    status = torch.empty(B, dtype=torch.int32, device=off.device)
+    _check(_lib.wfst_forward_backward(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(log_z),
+                                      _dptr(post), None, _dptr(status), _stream()))
+    return log_z, post, status
+
+
+def _make_log_partition():
+    import torch
+
+    class LogPartition(torch.autograd.Function):
+        """log Z_b of every sentence as a function of the arc scores.
+
+        forward(arc_score f32[A] (device), fst, offsets, tokens) -> log_z f32[B].
+        The scores are written into the FST's layouts (set_scores); backward
+        returns d loss / d arc_score = sum_b g_b E_b[count of each arc].
+        """
+
+        @staticmethod
+        def forward(ctx, arc_score, fst, offsets, tokens):
+            fst.set_scores(arc_score.detach().contiguous())
+            log_z, status, tape = forward(fst, offsets, tokens)
+            ctx.fst, ctx.tape = fst, tape
+            ctx.mark_non_differentiable(status)
+            return log_z, status
+
+        @staticmethod
+        def backward(ctx, grad_log_z, _grad_status):
+            g = backward(ctx.fst, ctx.tape, grad_log_z)
+            ctx.tape.free()
+            return g, None, None, None
+
+    return LogPartition
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _make_log_partition()
+        return getattr(_Lazy._cls, name)
+
+
+LogPartition = _Lazy()
+
+
+def log_partition(arc_score, fst, offsets, tokens):
+    """Differentiable log Z per sentence (returns (log_z, status))."""
+    return LogPartition.apply(arc_score, fst, offsets, tokens)

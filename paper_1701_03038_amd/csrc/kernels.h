@@ -1,0 +1,48 @@
+// Device-side views of the sliced layouts and the per-call batch state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.h"
+
+namespace wfst {
+
+struct DevLayout {
+    Elem *elem = nullptr;          // padded, slice-interleaved arc slots
+    int32_t *elem_arc = nullptr;   // arc id per slot (-1 padding)
+    SliceInfo *slice = nullptr;
+    int32_t *seg_key = nullptr;
+    SegChunk *seg_chunk = nullptr;
+    LabelInfo *label = nullptr;
+    int64_t n_elem = 0, n_slice = 0, n_seg = 0;
+    int32_t max_segs = 0, max_slots = 0, max_elems = 0, max_height = 0;
+};
+
+// What every batched sweep needs about the batch.
+struct BatchView {
+    int32_t B = 0;
+    int32_t M = 0;
+    int64_t N = 0;
+    const int32_t *offsets = nullptr;  // [B+1]
+    const int32_t *tokens = nullptr;   // [N]
+    const int32_t *order = nullptr;    // [B] processing order (longest first)
+    const int64_t *tok_off = nullptr;  // [N] compact per-step storage offsets (prefix of segment counts)
+    int32_t *queue = nullptr;          // work-queue head
+    int32_t *status = nullptr;         // [B]
+};
+
+// The forward-backward tape (compact: one value per (token, forward segment)).
+struct TapeView {
+    float *alpha = nullptr;    // alpha~_t on the destinations of w_t
+    float *beta = nullptr;     // beta~_t on the destinations of w_t
+    float *a_max = nullptr;    // [N] c_t: per-step normaliser of alpha~_t
+    double *a_log = nullptr;   // [N] C_t: log scale, true log alpha_t = alpha~_t - c_t + C_t
+    float *b_max = nullptr;    // [N]
+    double *b_log = nullptr;   // [N]
+    double *log_z = nullptr;   // [B]
+    double *log_z_bwd = nullptr;  // [B] log Z recomputed from beta_0[start]
+};
+
+}  // namespace wfst

@@ -1,0 +1,858 @@
+// HIP kernels for gfx950: the per-input-symbol semiring sparse matrix-vector
+// step (paper, section 5) run as persistent batched sweeps.
+//
+// One workgroup owns one sentence at a time, popped from a length-ordered
+// work queue; the state vector alpha_t (or beta_t) lives in LDS for the whole
+// sentence.  A step over input symbol a streams the sliced arc blocks of a
+// (coalesced 8-byte {state, score} loads, one chunk of a (label, key) segment
+// per lane), gathers the previous vector from LDS, reduces each chunk
+// serially, then combines multi-chunk segments in chunk order.  Every
+// reduction has a fixed order: there are no floating-point atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace wfst {
+
+#define WFST_NINF (-__builtin_huge_valf())
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// e^x through the hardware base-2 exponential (v_exp_f32).
+__device__ __forceinline__ float exp_e(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+// ln(x) through the hardware base-2 logarithm (v_log_f32).
+__device__ __forceinline__ float log_e(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+
+// Order-preserving map of a float onto uint32 (valid for every non-NaN value).
+__device__ __forceinline__ uint32_t ord_f32(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(uint32_t k)
+{
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ float wave_max_f(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// log-sum-exp accumulator (m, s): the set's LSE is m + ln s.  Merging is
+// written symmetrically so that merge(a, b) and merge(b, a) round the same.
+struct Lse {
+    float m, s;
+};
+__device__ __forceinline__ Lse lse_merge(Lse a, Lse b)
+{
+    if (a.m == WFST_NINF) return b;
+    if (b.m == WFST_NINF) return a;
+    const float big = fmaxf(a.m, b.m);
+    const float sbig = a.m >= b.m ? a.s : b.s;
+    const float ssmall = a.m >= b.m ? b.s : a.s;
+    const float small = fminf(a.m, b.m);
+    if (a.m == b.m) return Lse{big, a.s + b.s};
+    return Lse{big, sbig + ssmall * exp_e(small - big)};
+}
+// Online update with one finite value x: one exponential per value.
+__device__ __forceinline__ void lse_push(Lse &acc, float x)
+{
+    const float d = x - acc.m;  // +inf while acc is empty
+    const float e = exp_e(-fabsf(d));
+    if (d > 0.0f) {
+        acc.s = acc.s * e + 1.0f;
+        acc.m = x;
+    } else {
+        acc.s = acc.s + e;
+    }
+}
+__device__ __forceinline__ float lse_value(Lse a) { return a.s > 0.0f ? a.m + log_e(a.s) : WFST_NINF; }
+
+__device__ __forceinline__ Lse wave_lse(Lse v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        Lse w{__shfl_xor(v.m, o, 64), __shfl_xor(v.s, o, 64)};
+        v = lse_merge(v, w);
+    }
+    return v;
+}
+
+// Validates the sentence's offsets and tokens; returns a WFST_STATUS_* code.
+template <int NT>
+__device__ int check_sentence(const BatchView &bv, int b, int &o0, int &o1)
+{
+    o0 = bv.offsets[b];
+    o1 = bv.offsets[b + 1];
+    if (o0 < 0 || o1 < o0 || (int64_t)o1 > bv.N) return WFST_STATUS_BAD_INPUT;
+    int bad = 0;
+    for (int i = o0 + (int)threadIdx.x; i < o1; i += NT) {
+        const int a = bv.tokens[i];
+        bad |= (a < 0 || a >= bv.M);
+    }
+    return __syncthreads_or(bad) ? WFST_STATUS_BAD_TOKEN : WFST_STATUS_OK;
+}
+
+// =====================================================================
+// Viterbi (max-plus with back-pointers, paper section 5.1)
+// =====================================================================
+
+struct VEnt {
+    float v;      // alpha_t[q]
+    int32_t idx;  // segment index of q at step t (to chain back-pointers)
+};
+struct VPart {
+    float v;
+    int32_t pos;   // winning element
+    int32_t pred;  // segment index of the winner's source at the previous step
+};
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ final_score,
+              BatchView bv, int2 *__restrict__ bp, int32_t *__restrict__ path_tmp,
+              float *__restrict__ best_score, int32_t *__restrict__ best_arcs,
+              int32_t *__restrict__ best_olabels, const int32_t *__restrict__ olabel)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    VEnt *val0 = reinterpret_cast<VEnt *>(smem);
+    VEnt *val1 = val0 + (Q + 1);
+    VPart *part = reinterpret_cast<VPart *>(val1 + (Q + 1));
+    __shared__ int s_item;
+    __shared__ unsigned long long s_best[NW];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(bv.queue, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= bv.B) break;
+        const int b = bv.order[item];
+        int o0, o1;
+        const int st = check_sentence<NT>(bv, b, o0, o1);
+        if (st != WFST_STATUS_OK) {
+            if (tid == 0) {
+                bv.status[b] = st;
+                best_score[b] = WFST_NINF;
+            }
+            if (st == WFST_STATUS_BAD_TOKEN)
+                for (int i = o0 + tid; i < o1; i += NT) {
+                    best_arcs[i] = -1;
+                    if (best_olabels) best_olabels[i] = -1;
+                }
+            continue;
+        }
+        const int T = o1 - o0;
+        for (int q = tid; q <= Q; q += NT) {
+            val0[q] = VEnt{WFST_NINF, -1};
+            val1[q] = VEnt{WFST_NINF, -1};
+        }
+        __syncthreads();
+        if (tid == 0) val0[start] = VEnt{0.0f, 0};
+        __syncthreads();
+
+        for (int t = 1; t <= T; ++t) {
+            VEnt *prev = (t & 1) ? val0 : val1;
+            VEnt *cur = (t & 1) ? val1 : val0;
+            const int a = bv.tokens[o0 + t - 1];
+            const LabelInfo li = fl.label[a];
+            const int64_t toff = bv.tok_off[o0 + t - 1];
+            // phase 1: one chunk per lane
+            for (int s = wave; s < li.n_slices; s += NW) {
+                const SliceInfo si = fl.slice[li.slice_first + s];
+                if (lane < si.width) {
+                    const Elem *ep = fl.elem + si.base + lane;
+                    float best = WFST_NINF;
+                    int bpos = -1, bsrc = 0;
+                    for (int r = 0; r < si.height; ++r) {
+                        const Elem e = ep[r * si.width];
+                        const float v = prev[e.other].v + e.score;
+                        if (v > best) {
+                            best = v;
+                            bpos = si.base + r * si.width + lane;
+                            bsrc = e.other;
+                        }
+                    }
+                    const int pred = bpos >= 0 ? prev[bsrc].idx : -1;
+                    const int c = s * 64 + lane;
+                    if (c < li.n_slots) {
+                        part[c] = VPart{best, bpos, pred};
+                    } else {
+                        const int j = li.n_multi + (c - li.n_slots);
+                        const int d = fl.seg_key[li.seg_first + j];
+                        if (bpos >= 0) cur[d] = VEnt{best, j};
+                        bp[toff + j] = make_int2(bpos, pred);
+                    }
+                }
+            }
+            __syncthreads();
+            // phase 2: multi-chunk segments, chunks in order (lowest arc id wins ties)
+            for (int j = tid; j < li.n_multi; j += NT) {
+                const SegChunk sc = fl.seg_chunk[li.seg_first + j];
+                const int d = fl.seg_key[li.seg_first + j];
+                VPart w = part[sc.first];
+                for (int p = 1; p < sc.count; ++p) {
+                    const VPart x = part[sc.first + p];
+                    if (x.v > w.v) w = x;
+                }
+                if (w.pos >= 0) cur[d] = VEnt{w.v, j};
+                bp[toff + j] = make_int2(w.pos, w.pred);
+            }
+            // clear alpha_{t-1}: its buffer receives alpha_{t+1}
+            if (t == 1) {
+                if (tid == 0) prev[start].v = WFST_NINF;
+            } else {
+                const LabelInfo lp = fl.label[bv.tokens[o0 + t - 2]];
+                for (int j = tid; j < lp.n_segs; j += NT) prev[fl.seg_key[lp.seg_first + j]].v = WFST_NINF;
+            }
+            __syncthreads();
+        }
+
+        // final state: max of alpha_T[q] + f[q]; lowest state id on ties
+        VEnt *fin = (T & 1) ? val1 : val0;
+        unsigned long long key = 0ull;
+        if (T == 0) {
+            if (tid == 0) {
+                const float f = final_score[start];
+                const float v = 0.0f + f;
+                if (f != WFST_NINF && v != WFST_NINF)
+                    key = ((unsigned long long)ord_f32(v) << 32) | (0xffffffffu - (uint32_t)start);
+            }
+        } else {
+            const LabelInfo li = fl.label[bv.tokens[o1 - 1]];
+            for (int j = tid; j < li.n_segs; j += NT) {
+                const int d = fl.seg_key[li.seg_first + j];
+                const float x = fin[d].v;
+                const float f = final_score[d];
+                if (x == WFST_NINF || f == WFST_NINF) continue;
+                const float v = x + f;
+                if (v == WFST_NINF) continue;
+                const unsigned long long k = ((unsigned long long)ord_f32(v) << 32) | (0xffffffffu - (uint32_t)d);
+                key = k > key ? k : key;
+            }
+        }
+        key = wave_max_u64(key);
+        if (lane == 0) s_best[wave] = key;
+        __syncthreads();
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) best = s_best[w] > best ? s_best[w] : best;
+        if (best == 0ull) {
+            if (tid == 0) {
+                bv.status[b] = WFST_STATUS_NO_PATH;
+                best_score[b] = WFST_NINF;
+            }
+            for (int i = o0 + tid; i < o1; i += NT) {
+                best_arcs[i] = -1;
+                if (best_olabels) best_olabels[i] = -1;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (tid == 0) {
+            bv.status[b] = WFST_STATUS_OK;
+            best_score[b] = unord_f32((uint32_t)(best >> 32));
+            // backtrace (serial, on device: paper section 5.1)
+            const int qT = (int)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
+            int j = T > 0 ? fin[qT].idx : 0;
+            for (int t = T; t >= 1; --t) {
+                const int2 e = bp[bv.tok_off[o0 + t - 1] + j];
+                path_tmp[o0 + t - 1] = e.x;
+                j = e.y;
+            }
+        }
+        __syncthreads();
+        for (int i = o0 + tid; i < o1; i += NT) {
+            const int arc = fl.elem_arc[path_tmp[i]];
+            best_arcs[i] = arc;
+            if (best_olabels) best_olabels[i] = olabel[arc];
+        }
+        __syncthreads();
+    }
+}
+
+// =====================================================================
+// Forward / backward (log semiring, paper section 5.2, Algorithm 2)
+// =====================================================================
+
+// Phase 1 + 2 of one log-semiring step over a sliced layout.  prev holds the
+// previous vector (un-normalised; c_prev is subtracted on the fly), cur
+// receives LSE per segment key.  Returns this thread's max over what it wrote.
+// When tape != nullptr the value of segment j is also stored at tape[j].
+template <int NT>
+__device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &li, const float *prev,
+                                          float *cur, float c_prev, Lse *part, float *tape, int lane,
+                                          int wave)
+{
+    constexpr int NW = NT / 64;
+    float my_max = WFST_NINF;
+    for (int s = wave; s < li.n_slices; s += NW) {
+        const SliceInfo si = L.slice[li.slice_first + s];
+        if (lane < si.width) {
+            const Elem *ep = L.elem + si.base + lane;
+            Lse acc{WFST_NINF, 0.0f};
+            for (int r = 0; r < si.height; ++r) {
+                const Elem e = ep[r * si.width];
+                const float g = prev[e.other];
+                if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e.score);
+            }
+            const int c = s * 64 + lane;
+            if (c < li.n_slots) {
+                part[c] = acc;
+            } else {
+                const int j = li.n_multi + (c - li.n_slots);
+                const int d = L.seg_key[li.seg_first + j];
+                const float v = lse_value(acc);
+                cur[d] = v;
+                if (tape) tape[j] = v;
+                my_max = fmaxf(my_max, v);
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < li.n_multi; j += NT) {
+        const SegChunk sc = L.seg_chunk[li.seg_first + j];
+        const int d = L.seg_key[li.seg_first + j];
+        Lse acc = part[sc.first];
+        for (int p = 1; p < sc.count; ++p) {
+            const Lse x = part[sc.first + p];
+            if (x.m == WFST_NINF) continue;
+            if (acc.m == WFST_NINF) {
+                acc = x;
+            } else if (x.m > acc.m) {
+                acc.s = acc.s * exp_e(acc.m - x.m) + x.s;
+                acc.m = x.m;
+            } else {
+                acc.s = acc.s + x.s * exp_e(x.m - acc.m);
+            }
+        }
+        const float v = lse_value(acc);
+        cur[d] = v;
+        if (tape) tape[j] = v;
+        my_max = fmaxf(my_max, v);
+    }
+    return my_max;
+}
+
+// Reduce the per-thread maxima into cell (LDS, ordered uint); caller syncs.
+__device__ __forceinline__ void block_max_into(float v, uint32_t *cell, int lane)
+{
+    v = wave_max_f(v);
+    if (lane == 0) atomicMax(cell, ord_f32(v));
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ final_score,
+              BatchView bv, TapeView tp, float *__restrict__ log_z_out)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *val0 = reinterpret_cast<float *>(smem);
+    float *val1 = val0 + (Q + 1);
+    Lse *part = reinterpret_cast<Lse *>(val1 + (Q + 1));  // 2(Q+1) floats: 8-byte aligned
+    __shared__ int s_item;
+    __shared__ uint32_t s_cmax[3];
+    __shared__ Lse s_red[NW];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(bv.queue, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= bv.B) break;
+        const int b = bv.order[item];
+        int o0, o1;
+        const int st = check_sentence<NT>(bv, b, o0, o1);
+        if (st != WFST_STATUS_OK) {
+            if (tid == 0) {
+                bv.status[b] = st;
+                log_z_out[b] = WFST_NINF;
+                tp.log_z[b] = -__builtin_huge_val();
+            }
+            continue;
+        }
+        const int T = o1 - o0;
+        for (int q = tid; q <= Q; q += NT) {
+            val0[q] = WFST_NINF;
+            val1[q] = WFST_NINF;
+        }
+        if (tid < 3) s_cmax[tid] = 0u;
+        __syncthreads();
+        if (tid == 0) val0[start] = 0.0f;
+        __syncthreads();
+        float c_prev = 0.0f;
+        double C = 0.0;  // log scale of alpha (thread 0)
+        for (int t = 1; t <= T; ++t) {
+            float *prev = (t & 1) ? val0 : val1;
+            float *cur = (t & 1) ? val1 : val0;
+            const int i = o0 + t - 1;
+            const LabelInfo li = fl.label[bv.tokens[i]];
+            float *tape = tp.alpha + bv.tok_off[i];
+            const float mx = lse_step<NT>(fl, li, prev, cur, c_prev, part, tape, lane, wave);
+            if (t == 1) {
+                if (tid == 0) prev[start] = WFST_NINF;
+            } else {
+                const LabelInfo lp = fl.label[bv.tokens[i - 1]];
+                for (int j = tid; j < lp.n_segs; j += NT) prev[fl.seg_key[lp.seg_first + j]] = WFST_NINF;
+            }
+            if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
+            block_max_into(mx, &s_cmax[t % 3], lane);
+            __syncthreads();
+            float c = unord_f32(s_cmax[t % 3]);
+            if (!(c > WFST_NINF)) c = 0.0f;
+            if (tid == 0) {
+                C += (double)c;
+                tp.a_max[i] = c;
+                tp.a_log[i] = C;
+            }
+            c_prev = c;
+        }
+        // log Z = C_T + LSE_q(alpha^_T[q] + f[q])
+        Lse acc{WFST_NINF, 0.0f};
+        if (T == 0) {
+            if (tid == 0) {
+                const float f = final_score[start];
+                if (f != WFST_NINF) acc = Lse{f, 1.0f};
+            }
+        } else {
+            const float *fin = (T & 1) ? val1 : val0;
+            const LabelInfo li = fl.label[bv.tokens[o1 - 1]];
+            for (int j = tid; j < li.n_segs; j += NT) {
+                const int d = fl.seg_key[li.seg_first + j];
+                const float x = fin[d], f = final_score[d];
+                if (x == WFST_NINF || f == WFST_NINF) continue;
+                lse_push(acc, (x - c_prev) + f);
+            }
+        }
+        acc = wave_lse(acc);
+        if (lane == 0) s_red[wave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            Lse tot = s_red[0];
+            for (int w = 1; w < NW; ++w) tot = lse_merge(tot, s_red[w]);
+            const float lz32 = lse_value(tot);
+            if (lz32 == WFST_NINF) {
+                bv.status[b] = WFST_STATUS_NO_PATH;
+                log_z_out[b] = WFST_NINF;
+                tp.log_z[b] = -__builtin_huge_val();
+            } else {
+                const double lz = C + (double)lz32;
+                bv.status[b] = WFST_STATUS_OK;
+                log_z_out[b] = (float)lz;
+                tp.log_z[b] = lz;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
+               const float *__restrict__ final_score, const float *__restrict__ final_max,
+               BatchView bv, TapeView tp)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *val0 = reinterpret_cast<float *>(smem);
+    float *val1 = val0 + (Q + 1);
+    Lse *part = reinterpret_cast<Lse *>(val1 + (Q + 1));  // 2(Q+1) floats: 8-byte aligned
+    __shared__ int s_item;
+    __shared__ uint32_t s_cmax[3];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+    const float fmax0 = *final_max;
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(bv.queue, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= bv.B) break;
+        const int b = bv.order[item];
+        if (bv.status[b] != WFST_STATUS_OK) continue;
+        const int o0 = bv.offsets[b], o1 = bv.offsets[b + 1];
+        const int T = o1 - o0;
+        if (T == 0) {
+            if (tid == 0) tp.log_z_bwd[b] = (double)final_score[start];
+            continue;
+        }
+        float *vT = (T & 1) ? val1 : val0;
+        float *vO = (T & 1) ? val0 : val1;
+        for (int q = tid; q <= Q; q += NT) {
+            vT[q] = q < Q ? final_score[q] : WFST_NINF;
+            vO[q] = WFST_NINF;
+        }
+        if (tid < 3) s_cmax[tid] = 0u;
+        __syncthreads();
+        // beta_T on the destinations of w_T, for the expected counts
+        {
+            const LabelInfo lf = fl.label[bv.tokens[o1 - 1]];
+            float *tape = tp.beta + bv.tok_off[o1 - 1];
+            for (int j = tid; j < lf.n_segs; j += NT) tape[j] = vT[fl.seg_key[lf.seg_first + j]];
+            if (tid == 0) {
+                tp.b_max[o1 - 1] = fmax0;
+                tp.b_log[o1 - 1] = (double)fmax0;
+            }
+        }
+        float c_prev = fmax0;
+        double C = (double)fmax0;
+        for (int t = T; t >= 1; --t) {
+            float *prev = (t & 1) ? val1 : val0;  // beta~_t
+            float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
+            const int i = o0 + t - 1;
+            const LabelInfo li = rl.label[bv.tokens[i]];
+            const float mx = lse_step<NT>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave);
+            if (t == T) {
+                for (int q = tid; q < Q; q += NT) prev[q] = WFST_NINF;
+            } else {
+                const LabelInfo lp = rl.label[bv.tokens[i + 1]];
+                for (int j = tid; j < lp.n_segs; j += NT) prev[rl.seg_key[lp.seg_first + j]] = WFST_NINF;
+            }
+            if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
+            block_max_into(mx, &s_cmax[t % 3], lane);
+            __syncthreads();
+            float c = unord_f32(s_cmax[t % 3]);
+            if (!(c > WFST_NINF)) c = 0.0f;
+            if (tid == 0) C += (double)c;
+            if (t >= 2) {
+                const LabelInfo lf = fl.label[bv.tokens[i - 1]];
+                float *tape = tp.beta + bv.tok_off[i - 1];
+                for (int j = tid; j < lf.n_segs; j += NT) tape[j] = cur[fl.seg_key[lf.seg_first + j]];
+                if (tid == 0) {
+                    tp.b_max[i - 1] = c;
+                    tp.b_log[i - 1] = C;
+                }
+            } else if (tid == 0) {
+                const float x = cur[start];
+                tp.log_z_bwd[b] = x == WFST_NINF ? -__builtin_huge_val() : C + (double)(x - c);
+            }
+            c_prev = c;
+        }
+        __syncthreads();
+    }
+}
+
+// =====================================================================
+// Expected counts (paper, Algorithm 2 last loop): grouped by input label so
+// that each arc's sum over the visits of its label is taken in a fixed
+// order, without atomics.
+// =====================================================================
+
+struct CEnt {
+    float v;
+    int32_t stamp;
+};
+
+struct CountItem {
+    int32_t first, last;  // range in the label-sorted visit list
+    int32_t label;
+    int32_t split;        // 1 when the label's visits span several items
+};
+
+// CH is the layout's chunk size (slice heights never exceed it); each lane
+// keeps KPP * CH = 64 accumulators in registers, so one pass covers KPP
+// slices per wavefront and wide labels take several passes over their visits.
+template <int NT, int CH>
+__global__ void __launch_bounds__(NT)
+counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
+              const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
+              const int32_t *__restrict__ visits, const int32_t *__restrict__ tok_sent,
+              const float *__restrict__ grad_log_z, float *__restrict__ grad,
+              float *__restrict__ partial, int32_t *__restrict__ item_slot,
+              int32_t *__restrict__ slot_counter)
+{
+    constexpr int NW = NT / 64;
+    constexpr int KPP = 64 / CH;
+    constexpr int MAXR = KPP * CH;
+    extern __shared__ __align__(16) unsigned char smem[];
+    CEnt *den0 = reinterpret_cast<CEnt *>(smem);
+    CEnt *den1 = den0 + (Q + 1);
+    int32_t *chunk_seg = reinterpret_cast<int32_t *>(den1 + (Q + 1));
+    __shared__ int s_slot;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+    for (int q = tid; q <= Q; q += NT) {
+        den0[q] = CEnt{WFST_NINF, -1};
+        den1[q] = CEnt{WFST_NINF, -1};
+    }
+    const int nit = *n_items;
+    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+        const CountItem ci = items[it];
+        const LabelInfo li = fl.label[ci.label];
+        __syncthreads();
+        for (int j = tid; j < li.n_multi; j += NT) {
+            const SegChunk sc = fl.seg_chunk[li.seg_first + j];
+            for (int p = 0; p < sc.count; ++p) chunk_seg[sc.first + p] = j;
+        }
+        if (ci.split && tid == 0) {
+            s_slot = atomicAdd(slot_counter, 1);
+            item_slot[it] = s_slot;
+        }
+        __syncthreads();
+        const int slot = ci.split ? s_slot : -1;
+        const int passes = (li.n_slices + NW * KPP - 1) / (NW * KPP);
+        for (int pass = 0; pass < passes; ++pass) {
+            __syncthreads();  // the previous pass may still read either density buffer
+            float acc[MAXR];
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) acc[r] = 0.0f;
+            for (int v = ci.first; v < ci.last; ++v) {
+                const int i = visits[v];
+                const int b = tok_sent[i];
+                const bool live = bv.status[b] == WFST_STATUS_OK;
+                CEnt *den = (v & 1) ? den1 : den0;
+                float o = 0.0f, g = 1.0f;
+                int t = 0;
+                if (live) {
+                    t = i - bv.offsets[b] + 1;
+                    const double aC = t > 1 ? tp.a_log[i - 1] : 0.0;
+                    o = (float)(aC + tp.b_log[i] - tp.log_z[b]);
+                    g = grad_log_z ? grad_log_z[b] : 1.0f;
+                    if (t == 1) {
+                        if (tid == 0) den[start] = CEnt{0.0f, v};
+                    } else {
+                        const LabelInfo lp = fl.label[bv.tokens[i - 1]];
+                        const float *ta = tp.alpha + bv.tok_off[i - 1];
+                        const float cm = tp.a_max[i - 1];
+                        for (int j = tid; j < lp.n_segs; j += NT)
+                            den[fl.seg_key[lp.seg_first + j]] = CEnt{ta[j] - cm, v};
+                    }
+                }
+                __syncthreads();
+                if (!live) continue;
+                const float *tb = tp.beta + bv.tok_off[i];
+                const float bm = tp.b_max[i];
+#pragma unroll
+                for (int k = 0; k < KPP; ++k) {
+                    const int s = (pass * KPP + k) * NW + wave;
+                    if (s < li.n_slices) {
+                        const SliceInfo si = fl.slice[li.slice_first + s];
+                        if (lane < si.width) {
+                            const int c = s * 64 + lane;
+                            const int j = c < li.n_slots ? chunk_seg[c] : li.n_multi + (c - li.n_slots);
+                            const float bh = tb[j] - bm;
+                            const Elem *ep = fl.elem + si.base + lane;
+#pragma unroll
+                            for (int r = 0; r < CH; ++r) {
+                                if (r < si.height) {
+                                    const Elem e = ep[r * si.width];
+                                    const CEnt ae = den[e.other];
+                                    const float x = ((ae.v + e.score) + bh) + o;
+                                    const float add = g * exp_e(x);
+                                    acc[k * CH + r] += ae.stamp == v ? add : 0.0f;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            // write this pass's arcs
+#pragma unroll
+            for (int k = 0; k < KPP; ++k) {
+                const int s = (pass * KPP + k) * NW + wave;
+                if (s < li.n_slices) {
+                    const SliceInfo si = fl.slice[li.slice_first + s];
+                    if (lane < si.width) {
+#pragma unroll
+                        for (int r = 0; r < CH; ++r) {
+                            if (r < si.height) {
+                                const int pos = si.base + r * si.width + lane;
+                                const float val = acc[k * CH + r];
+                                if (slot < 0) {
+                                    const int arc = fl.elem_arc[pos];
+                                    if (arc >= 0) grad[arc] = val;
+                                } else {
+                                    partial[(int64_t)slot * fl.max_elems + (pos - li.elem_first)] = val;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Sums the partial counts of labels whose visits span several items, in item order.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+counts_fixup(DevLayout fl, const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
+             const int32_t *__restrict__ item_slot, const float *__restrict__ partial,
+             float *__restrict__ grad)
+{
+    const int nit = *n_items;
+    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+        const CountItem ci = items[it];
+        if (!ci.split) continue;
+        if (it > 0 && items[it - 1].label == ci.label) continue;  // first item of the label only
+        int last = it;
+        while (last + 1 < nit && items[last + 1].label == ci.label) ++last;
+        const LabelInfo li = fl.label[ci.label];
+        for (int e = threadIdx.x; e < li.n_elems; e += NT) {
+            float s = 0.0f;
+            for (int k = it; k <= last; ++k) s += partial[(int64_t)item_slot[k] * fl.max_elems + e];
+            const int arc = fl.elem_arc[li.elem_first + e];
+            if (arc >= 0) grad[arc] = s;
+        }
+    }
+}
+
+// =====================================================================
+// Small helpers
+// =====================================================================
+
+__global__ void fill_f32(float *__restrict__ p, int64_t n, float v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void copy_f32(float *__restrict__ dst, const float *__restrict__ src, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// per-token segment count of the forward layout (0 for an invalid token)
+__global__ void token_segments(const int32_t *__restrict__ tokens, int64_t N, const LabelInfo *__restrict__ label,
+                               int32_t M, int64_t *__restrict__ out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int a = tokens[i];
+        out[i] = (a >= 0 && a < M) ? label[a].n_segs : 0;
+    }
+}
+
+// token -> sentence, and visit keys (label) for grouping
+__global__ void token_owner(const int32_t *__restrict__ offsets, int32_t B, int64_t N,
+                            const int32_t *__restrict__ tokens, int32_t *__restrict__ tok_sent,
+                            int32_t *__restrict__ vis_key, int32_t *__restrict__ vis_idx, int32_t M)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = B;  // last b with offsets[b] <= i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (offsets[mid] <= i) lo = mid; else hi = mid;
+        }
+        tok_sent[i] = lo;
+        const int a = tokens[i];
+        vis_key[i] = (a >= 0 && a < M) ? a : M;  // invalid tokens sort last
+        vis_idx[i] = (int)i;
+    }
+}
+
+// one thread per label: visit range in the sorted list and its item count
+__global__ void label_groups(const int32_t *__restrict__ skeys, int64_t N, int32_t M, int32_t V,
+                             int32_t *__restrict__ grp_lo, int32_t *__restrict__ grp_n,
+                             int32_t *__restrict__ n_items_per_label)
+{
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < M; a += gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = N;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (skeys[mid] < a) lo = mid + 1; else hi = mid;
+        }
+        int64_t lo2 = lo, hi2 = N;
+        while (lo2 < hi2) {
+            const int64_t mid = (lo2 + hi2) >> 1;
+            if (skeys[mid] <= a) lo2 = mid + 1; else hi2 = mid;
+        }
+        const int n = (int)(lo2 - lo);
+        grp_lo[a] = (int)lo;
+        grp_n[a] = n;
+        n_items_per_label[a] = (n + V - 1) / V;
+    }
+}
+
+__global__ void label_items(const int32_t *__restrict__ grp_lo, const int32_t *__restrict__ grp_n,
+                            const int32_t *__restrict__ n_items_per_label,
+                            const int32_t *__restrict__ item_base, int32_t M, int32_t V,
+                            CountItem *__restrict__ items, int32_t *__restrict__ n_items)
+{
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < M; a += gridDim.x * blockDim.x) {
+        const int k = n_items_per_label[a];
+        const int base = item_base[a];
+        for (int x = 0; x < k; ++x) {
+            const int f = grp_lo[a] + x * V;
+            const int l = min(grp_lo[a] + grp_n[a], f + V);
+            items[base + x] = CountItem{f, l, a, k > 1 ? 1 : 0};
+        }
+        if (a == M - 1) *n_items = base + k;
+    }
+}
+
+// new scores into a layout through its element -> arc map
+__global__ void scatter_scores(Elem *__restrict__ elem, const int32_t *__restrict__ elem_arc, int64_t n,
+                               const float *__restrict__ score)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int arc = elem_arc[e];
+        if (arc >= 0) {
+            const float s = score[arc];
+            elem[e].score = s == 0.0f ? 0.0f : s;
+        }
+    }
+}
+
+__global__ void final_max_kernel(const float *__restrict__ fin, int32_t Q, float *__restrict__ out)
+{
+    __shared__ float red[1024];
+    float m = WFST_NINF;
+    for (int q = threadIdx.x; q < Q; q += blockDim.x) m = fmaxf(m, fin[q]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] > WFST_NINF ? red[0] : 0.0f;
+}
+
+}  // namespace wfst

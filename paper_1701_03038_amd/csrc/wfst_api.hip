@@ -1,0 +1,798 @@
+// C ABI of the library (declared in include/wfst.h): argument validation,
+// device layouts, workspace and kernel launches.
+//
+// Memory: every FST owns its layouts plus a grow-only workspace and a pool of
+// tape buffers.  A call only allocates when it needs more than any earlier
+// call on the same FST (then it synchronises its stream, frees the smaller
+// buffer and allocates a larger one); in steady state calls allocate nothing.
+// Consequently calls on one FST must not overlap: issue them on one stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/wfst.h"
+#include "kernels.h"
+#include "layout.h"
+#include "prims.hip"
+#include "sweeps.hip"
+
+using namespace wfst;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return set_err(WFST_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)                       \
+    do {                                \
+        int rc_ = (expr);               \
+        if (rc_ != WFST_OK) return rc_; \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int grid_for(int64_t n, int nt, int cap = 65535)
+{
+    const int64_t g = (n + nt - 1) / nt;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// A grow-only device buffer.
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+int ensure(Buf &b, size_t bytes, hipStream_t s)
+{
+    bytes = std::max<size_t>(bytes, 256);
+    if (b.cap >= bytes) return WFST_OK;
+    if (b.p) {
+        HIP_OK(hipStreamSynchronize(s));
+        HIP_OK(hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    const size_t want = bytes + bytes / 4;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return set_err(WFST_ENOMEM, "hipMalloc(" + std::to_string(want) + " bytes): " + hipGetErrorString(e));
+    }
+    b.cap = want;
+    return WFST_OK;
+}
+
+template <class T>
+int ensure_t(Buf &b, int64_t count, hipStream_t s, T **out)
+{
+    TRY(ensure(b, (size_t)std::max<int64_t>(count, 1) * sizeof(T), s));
+    *out = reinterpret_cast<T *>(b.p);
+    return WFST_OK;
+}
+
+enum WsSlot {
+    W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
+    W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
+    W_PARTIAL, W_NUM
+};
+
+// small device counters kept together (one allocation)
+enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_TOTAL = 4 /* int64 at byte 16 */, C_COUNT = 8 };
+
+struct TapeBufs {
+    Buf order, tok_off, alpha, a_max, a_log, log_z, tiles, total;
+};
+
+}  // namespace
+
+struct wfst_fst {
+    int device = 0;
+    int32_t Q = 0, M = 0, start = 0, chunk = 16, nt = 256;
+    int64_t A = 0;
+    DevLayout fwd, rev;
+    float *final_score = nullptr;
+    float *final_max = nullptr;
+    int32_t *olabel = nullptr;
+    int64_t bytes = 0;
+    int cu_count = 0;
+    size_t max_lds = 0;
+    std::vector<void *> allocs;
+    Buf ws[W_NUM];
+    std::vector<TapeBufs *> tape_pool;
+};
+
+struct wfst_tape {
+    const wfst_fst *fst = nullptr;
+    int32_t B = 0;
+    int64_t N = 0, total = 0;
+    const int32_t *offsets = nullptr, *tokens = nullptr;
+    int32_t *status = nullptr;
+    TapeBufs *bufs = nullptr;
+    int32_t *order = nullptr;
+    int64_t *tok_off = nullptr;
+    float *alpha = nullptr, *a_max = nullptr;
+    double *a_log = nullptr, *log_z = nullptr;
+};
+
+namespace {
+
+template <class T>
+int dev_upload(wfst_fst *f, T **dst, const T *src, int64_t count, hipStream_t s)
+{
+    const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    void *p = nullptr;
+    HIP_OK(hipMalloc(&p, bytes));
+    f->allocs.push_back(p);
+    f->bytes += (int64_t)bytes;
+    if (src && count > 0) HIP_OK(hipMemcpyAsync(p, src, (size_t)count * sizeof(T), hipMemcpyHostToDevice, s));
+    *dst = reinterpret_cast<T *>(p);
+    return WFST_OK;
+}
+
+int upload_layout(wfst_fst *f, const HostLayout &h, DevLayout &d, hipStream_t s)
+{
+    TRY(dev_upload(f, &d.elem, h.elem.data(), (int64_t)h.elem.size(), s));
+    TRY(dev_upload(f, &d.elem_arc, h.elem_arc.data(), (int64_t)h.elem_arc.size(), s));
+    TRY(dev_upload(f, &d.slice, h.slice.data(), (int64_t)h.slice.size(), s));
+    TRY(dev_upload(f, &d.seg_key, h.seg_key.data(), (int64_t)h.seg_key.size(), s));
+    TRY(dev_upload(f, &d.seg_chunk, h.seg_chunk.data(), (int64_t)h.seg_chunk.size(), s));
+    TRY(dev_upload(f, &d.label, h.label.data(), (int64_t)h.label.size(), s));
+    d.n_elem = (int64_t)h.elem.size();
+    d.n_slice = (int64_t)h.slice.size();
+    d.n_seg = (int64_t)h.seg_key.size();
+    d.max_segs = h.max_segs;
+    d.max_slots = h.max_slots;
+    d.max_elems = h.max_elems;
+    d.max_height = h.max_height;
+    return WFST_OK;
+}
+
+void free_buf(Buf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+void free_fst(wfst_fst *f)
+{
+    if (!f) return;
+    int cur = 0;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != f->device;
+    if (other) (void)hipSetDevice(f->device);
+    (void)hipDeviceSynchronize();
+    for (void *p : f->allocs) (void)hipFree(p);
+    for (Buf &b : f->ws) free_buf(b);
+    for (TapeBufs *t : f->tape_pool) {
+        for (Buf *b : {&t->order, &t->tok_off, &t->alpha, &t->a_max, &t->a_log, &t->log_z, &t->tiles, &t->total})
+            free_buf(*b);
+        delete t;
+    }
+    if (other) (void)hipSetDevice(cur);
+    delete f;
+}
+
+// LDS bytes of each kernel for this FST.
+size_t lds_viterbi(const wfst_fst *f)
+{
+    return (size_t)(f->Q + 1) * 2 * sizeof(VEnt) + (size_t)std::max(f->fwd.max_slots, 1) * sizeof(VPart);
+}
+size_t lds_lse(const wfst_fst *f, const DevLayout &l)
+{
+    return (size_t)(f->Q + 1) * 2 * sizeof(float) + (size_t)std::max(l.max_slots, 1) * sizeof(Lse);
+}
+size_t lds_counts(const wfst_fst *f)
+{
+    return (size_t)(f->Q + 1) * 2 * sizeof(CEnt) + (size_t)std::max(f->fwd.max_slots, 1) * sizeof(int32_t);
+}
+
+template <class K>
+int persistent_grid(const wfst_fst *f, K kernel, int nt, size_t lds, int64_t work, int *grid)
+{
+    if (lds > f->max_lds)
+        return set_err(WFST_EUNSUPPORTED, "FST needs " + std::to_string(lds) +
+                                              " bytes of LDS per workgroup; the device offers " +
+                                              std::to_string(f->max_lds));
+    if (lds > 65536)
+        HIP_OK(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, lds));
+    if (per_cu < 1) return set_err(WFST_EUNSUPPORTED, "kernel does not fit on a compute unit");
+    *grid = (int)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)per_cu * f->cu_count));
+    return WFST_OK;
+}
+
+int check_batch(const wfst_fst *f, int32_t batch, int64_t num_tokens, const void *offsets, const void *tokens)
+{
+    if (!f) return set_err(WFST_EINVAL, "fst is NULL");
+    if (batch < 0) return set_err(WFST_EINVAL, "batch < 0");
+    if (num_tokens < 0 || num_tokens >= INT32_MAX) return set_err(WFST_EINVAL, "num_tokens outside [0, 2^31-1)");
+    if (batch > 0 && !offsets) return set_err(WFST_EINVAL, "offsets is NULL");
+    if (num_tokens > 0 && !tokens) return set_err(WFST_EINVAL, "tokens is NULL");
+    return WFST_OK;
+}
+
+// Exclusive prefix sum of src over n elements into out; the grand total is
+// written to *total (device) when total != nullptr.  tiles: scratch of
+// ceil(n / kScanTile) int64.
+template <class OutT>
+int launch_scan(hipStream_t s, ScanSource src, int64_t n, int64_t *tiles, OutT *out, int64_t *total)
+{
+    const int64_t ntiles = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+    if (n > 0) hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, src, n, tiles);
+    else hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, tiles, (int64_t)1, (int64_t)0);
+    hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(kScanThreads), 0, s, tiles, ntiles, total);
+    if (n > 0) hipLaunchKernelGGL((scan_apply<OutT>), dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, src, n,
+                                  (const int64_t *)tiles, out);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+inline int64_t scan_tiles_for(int64_t n) { return std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile); }
+
+struct Plan {
+    int32_t *order = nullptr;
+    int64_t *tok_off = nullptr;
+    int64_t total = 0;  // capacity needed for compact per-(token, segment) storage
+};
+
+// Sentence order (length buckets, longest first) and per-token offsets of the
+// compact per-step storage.  The storage size is the exact total (read back,
+// one synchronisation) when the cheap bound N * max_segs exceeds `bound_cap`.
+int make_plan(const wfst_fst *f, hipStream_t s, int32_t B, int64_t N, const int32_t *offsets,
+              const int32_t *tokens, int32_t *order, int64_t *tok_off, int64_t *tiles, int64_t *dev_total,
+              int64_t bound_cap_elems, Plan &p)
+{
+    p.order = order;
+    p.tok_off = tok_off;
+    hipLaunchKernelGGL(order_by_length, dim3(1), dim3(1024), 0, s, offsets, B, order);
+    ScanSource src;
+    src.tokens = tokens;
+    src.label = f->fwd.label;
+    src.M = f->M;
+    TRY(launch_scan<int64_t>(s, src, N, tiles, tok_off, dev_total));
+    const int64_t bound = N * (int64_t)std::max(f->fwd.max_segs, 1);
+    if (bound <= bound_cap_elems) {
+        p.total = bound;
+    } else {
+        int64_t t = 0;
+        HIP_OK(hipMemcpyAsync(&t, dev_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        p.total = t;
+    }
+    return WFST_OK;
+}
+
+constexpr int64_t kBoundCapBytes = (int64_t)2 << 30;
+
+template <int NT>
+int launch_viterbi(const wfst_fst *f, hipStream_t s, const BatchView &bv, int2 *bp, int32_t *path_tmp,
+                   float *best_score, int32_t *best_arcs, int32_t *best_olabels)
+{
+    const size_t lds = lds_viterbi(f);
+    int grid = 0;
+    TRY(persistent_grid(f, viterbi_sweep<NT>, NT, lds, bv.B, &grid));
+    hipLaunchKernelGGL((viterbi_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start,
+                       (const float *)f->final_score, bv, bp, path_tmp, best_score, best_arcs, best_olabels,
+                       (const int32_t *)f->olabel);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+template <int NT>
+int launch_forward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, float *log_z)
+{
+    const size_t lds = lds_lse(f, f->fwd);
+    int grid = 0;
+    TRY(persistent_grid(f, forward_sweep<NT>, NT, lds, bv.B, &grid));
+    hipLaunchKernelGGL((forward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start,
+                       (const float *)f->final_score, bv, tp, log_z);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+template <int NT>
+int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp)
+{
+    const size_t lds = lds_lse(f, f->rev);
+    int grid = 0;
+    TRY(persistent_grid(f, backward_sweep<NT>, NT, lds, bv.B, &grid));
+    hipLaunchKernelGGL((backward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start,
+                       (const float *)f->final_score, (const float *)f->final_max, bv, tp);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+template <int CH>
+int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
+                     const CountItem *items, const int32_t *n_items, int64_t items_bound, const int32_t *visits,
+                     const int32_t *tok_sent, const float *g, float *grad, float *partial, int32_t *item_slot,
+                     int32_t *slot_counter)
+{
+    constexpr int NT = 256;
+    const size_t lds = lds_counts(f);
+    int grid = 0;
+    TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
+    hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start, bv, tp,
+                       items, n_items, visits, tok_sent, g, grad, partial, item_slot, slot_counter);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+#define DISPATCH_NT(rc, nt, fn, ...)                  \
+    switch (nt) {                                     \
+    case 64: rc = fn<64>(__VA_ARGS__); break;         \
+    case 128: rc = fn<128>(__VA_ARGS__); break;       \
+    case 256: rc = fn<256>(__VA_ARGS__); break;       \
+    case 512: rc = fn<512>(__VA_ARGS__); break;       \
+    default: rc = fn<1024>(__VA_ARGS__); break;       \
+    }
+
+BatchView make_view(const wfst_fst *f, int32_t B, int64_t N, const int32_t *offsets, const int32_t *tokens,
+                    const int32_t *order, const int64_t *tok_off, int32_t *queue, int32_t *status)
+{
+    BatchView bv;
+    bv.B = B;
+    bv.M = f->M;
+    bv.N = N;
+    bv.offsets = offsets;
+    bv.tokens = tokens;
+    bv.order = order;
+    bv.tok_off = tok_off;
+    bv.queue = queue;
+    bv.status = status;
+    return bv;
+}
+
+// Stable sort of token positions by label: visits[] lists positions grouped by
+// label, in increasing position inside each label; skeys[] their labels.
+int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, const int32_t *offsets, int32_t B,
+                int32_t **visits_out, int32_t **skeys_out, int32_t *tok_sent)
+{
+    int32_t *k0, *k1, *v0, *v1;
+    TRY(ensure_t(f->ws[W_KEY0], N, s, &k0));
+    TRY(ensure_t(f->ws[W_KEY1], N, s, &k1));
+    TRY(ensure_t(f->ws[W_VAL0], N, s, &v0));
+    TRY(ensure_t(f->ws[W_VAL1], N, s, &v1));
+    hipLaunchKernelGGL(token_owner, dim3(grid_for(N, 256)), dim3(256), 0, s, offsets, B, N, tokens, tok_sent, k0,
+                       v0, f->M);
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) <= (int64_t)f->M) ++bits;
+    const int passes = (bits + 7) / 8;
+    const int64_t ntiles = (N + kSortTile - 1) / kSortTile;
+    int64_t *hist, *tiles;
+    TRY(ensure_t(f->ws[W_HIST], 256 * ntiles, s, &hist));
+    TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(256 * ntiles), s, &tiles));
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0, N,
+                           shift, ntiles, hist);
+        ScanSource src;
+        src.i64 = hist;
+        TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
+        hipLaunchKernelGGL(radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
+                           (const int32_t *)v0, N, shift, ntiles, (const int64_t *)hist, k1, v1);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    HIP_OK(hipGetLastError());
+    *skeys_out = k0;
+    *visits_out = v0;
+    return WFST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wfst_last_error(void) { return g_err.c_str(); }
+
+int wfst_layout_host(int32_t num_states, int32_t num_ilabels, int64_t num_arcs, const int32_t *src,
+                     const int32_t *dst, const int32_t *ilabel, int32_t direction, int32_t chunk_arcs,
+                     int64_t *sizes, int32_t *elem_other, int32_t *elem_arc, int32_t *slice_info,
+                     int32_t *seg_info, int32_t *label_slice, int32_t *label_seg)
+{
+    try {
+        if (num_states <= 0 || num_ilabels <= 0 || num_arcs < 0 || num_arcs >= INT32_MAX || !sizes)
+            return set_err(WFST_EINVAL, "bad sizes");
+        if (num_arcs > 0 && (!src || !dst || !ilabel)) return set_err(WFST_EINVAL, "NULL arc array");
+        if (direction != 0 && direction != 1) return set_err(WFST_EINVAL, "direction must be 0 or 1");
+        for (int64_t k = 0; k < num_arcs; ++k)
+            if (src[k] < 0 || src[k] >= num_states || dst[k] < 0 || dst[k] >= num_states || ilabel[k] < 0 ||
+                ilabel[k] >= num_ilabels)
+                return set_err(WFST_EINVAL, "arc " + std::to_string(k) + " out of range");
+        HostLayout h;
+        std::string err;
+        const int32_t L = chunk_arcs > 0 ? chunk_arcs : auto_chunk(num_states, num_ilabels, num_arcs);
+        int rc = build_layout(num_states, num_ilabels, num_arcs, src, dst, ilabel, nullptr, direction, L, h, err);
+        if (rc != WFST_OK) return set_err(rc, err);
+        sizes[0] = (int64_t)h.elem.size();
+        sizes[1] = (int64_t)h.slice.size();
+        sizes[2] = (int64_t)h.seg_key.size();
+        if (elem_other)
+            for (size_t e = 0; e < h.elem.size(); ++e) elem_other[e] = h.elem[e].other;
+        if (elem_arc) std::memcpy(elem_arc, h.elem_arc.data(), h.elem_arc.size() * sizeof(int32_t));
+        if (slice_info)
+            for (size_t x = 0; x < h.slice.size(); ++x) {
+                slice_info[4 * x + 0] = h.slice[x].base;
+                slice_info[4 * x + 1] = h.slice[x].height;
+                slice_info[4 * x + 2] = h.slice[x].width;
+                slice_info[4 * x + 3] = h.slice[x].label;
+            }
+        if (seg_info || label_slice || label_seg) {
+            for (int32_t a = 0; a < num_ilabels; ++a) {
+                const LabelInfo &li = h.label[(size_t)a];
+                if (label_slice) label_slice[a] = li.slice_first;
+                if (label_seg) label_seg[a] = li.seg_first;
+                if (seg_info)
+                    for (int32_t j = 0; j < li.n_segs; ++j) {
+                        const size_t g = (size_t)li.seg_first + j;
+                        seg_info[4 * g + 0] = h.seg_key[g];
+                        seg_info[4 * g + 1] = h.seg_chunk[g].first;
+                        seg_info[4 * g + 2] = h.seg_chunk[g].count;
+                        seg_info[4 * g + 3] = a;
+                    }
+            }
+            if (label_slice) label_slice[num_ilabels] = (int32_t)h.slice.size();
+            if (label_seg) label_seg[num_ilabels] = (int32_t)h.seg_key.size();
+        }
+        return WFST_OK;
+    } catch (const std::bad_alloc &) {
+        return set_err(WFST_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_err(WFST_EINVAL, e.what());
+    }
+}
+
+int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int64_t num_arcs,
+                    const int32_t *src, const int32_t *dst, const int32_t *ilabel, const int32_t *olabel,
+                    const float *arc_score, const float *final_score, const wfst_options *options,
+                    void *stream, wfst_fst **out)
+{
+    if (!out) return set_err(WFST_EINVAL, "out is NULL");
+    *out = nullptr;
+    try {
+        if (num_states <= 0 || num_states >= INT32_MAX - 1) return set_err(WFST_EINVAL, "num_states out of range");
+        if (num_ilabels <= 0) return set_err(WFST_EINVAL, "num_ilabels must be positive");
+        if (start < 0 || start >= num_states) return set_err(WFST_EINVAL, "start out of range");
+        if (num_arcs < 0 || num_arcs >= INT32_MAX) return set_err(WFST_EUNSUPPORTED, "num_arcs must be < 2^31-1");
+        if (num_arcs > 0 && (!src || !dst || !ilabel || !arc_score)) return set_err(WFST_EINVAL, "NULL arc array");
+        if (!final_score) return set_err(WFST_EINVAL, "final_score is NULL");
+        for (int64_t k = 0; k < num_arcs; ++k) {
+            if (src[k] < 0 || src[k] >= num_states || dst[k] < 0 || dst[k] >= num_states)
+                return set_err(WFST_EINVAL, "arc " + std::to_string(k) + ": state out of range");
+            if (ilabel[k] < 0 || ilabel[k] >= num_ilabels)
+                return set_err(WFST_EINVAL, "arc " + std::to_string(k) + ": ilabel out of range");
+            if (!std::isfinite(arc_score[k]))
+                return set_err(WFST_EINVAL, "arc " + std::to_string(k) + ": score is not finite");
+        }
+        for (int32_t q = 0; q < num_states; ++q)
+            if (std::isnan(final_score[q]) || final_score[q] == INFINITY)
+                return set_err(WFST_EINVAL, "final_score[" + std::to_string(q) + "] is NaN or +inf");
+        wfst_options opt{};
+        if (options) opt = *options;
+        int32_t L = opt.chunk_arcs > 0 ? opt.chunk_arcs : auto_chunk(num_states, num_ilabels, num_arcs);
+        if (L > 64) return set_err(WFST_EINVAL, "chunk_arcs must be <= 64");
+        int nt = opt.threads_per_sentence > 0 ? opt.threads_per_sentence : 256;
+        if (nt != 64 && nt != 128 && nt != 256 && nt != 512 && nt != 1024)
+            return set_err(WFST_EINVAL, "threads_per_sentence must be 64, 128, 256, 512 or 1024");
+
+        hipStream_t s = as_stream(stream);
+        wfst_fst *f = new wfst_fst();
+        f->Q = num_states;
+        f->M = num_ilabels;
+        f->start = start;
+        f->A = num_arcs;
+        f->chunk = L;
+        f->nt = nt;
+        if (hipGetDevice(&f->device) != hipSuccess) {
+            delete f;
+            return set_err(WFST_EHIP, "hipGetDevice failed");
+        }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, f->device) != hipSuccess) {
+            delete f;
+            return set_err(WFST_EHIP, "hipGetDeviceProperties failed");
+        }
+        f->cu_count = prop.multiProcessorCount;
+        f->max_lds = prop.sharedMemPerBlock;
+        std::string err;
+        int rc;
+        {
+            HostLayout h;
+            rc = build_layout(num_states, num_ilabels, num_arcs, src, dst, ilabel, arc_score, 0, L, h, err);
+            if (rc != WFST_OK) rc = set_err(rc, err);
+            if (rc == WFST_OK) rc = upload_layout(f, h, f->fwd, s);
+            if (rc == WFST_OK && hipStreamSynchronize(s) != hipSuccess) rc = set_err(WFST_EHIP, "upload failed");
+        }
+        if (rc == WFST_OK) {
+            HostLayout h;
+            rc = build_layout(num_states, num_ilabels, num_arcs, src, dst, ilabel, arc_score, 1, L, h, err);
+            if (rc != WFST_OK) rc = set_err(rc, err);
+            if (rc == WFST_OK) rc = upload_layout(f, h, f->rev, s);
+            if (rc == WFST_OK && hipStreamSynchronize(s) != hipSuccess) rc = set_err(WFST_EHIP, "upload failed");
+        }
+        if (rc == WFST_OK) rc = dev_upload(f, &f->final_score, final_score, num_states, s);
+        if (rc == WFST_OK) rc = dev_upload<float>(f, &f->final_max, nullptr, 1, s);
+        if (rc == WFST_OK && olabel) rc = dev_upload(f, &f->olabel, olabel, num_arcs, s);
+        if (rc == WFST_OK) {
+            hipLaunchKernelGGL(final_max_kernel, dim3(1), dim3(1024), 0, s, (const float *)f->final_score, f->Q,
+                               f->final_max);
+            if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+                rc = set_err(WFST_EHIP, "final_max kernel failed");
+        }
+        if (rc != WFST_OK) {
+            free_fst(f);
+            return rc;
+        }
+        *out = f;
+        return WFST_OK;
+    } catch (const std::bad_alloc &) {
+        return set_err(WFST_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_err(WFST_EINVAL, e.what());
+    }
+}
+
+int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *final_score_dev, void *stream)
+{
+    if (!f) return set_err(WFST_EINVAL, "fst is NULL");
+    hipStream_t s = as_stream(stream);
+    if (arc_score_dev && f->A > 0) {
+        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->fwd.n_elem, 256, 8192)), dim3(256), 0, s, f->fwd.elem,
+                           (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, arc_score_dev);
+        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->rev.n_elem, 256, 8192)), dim3(256), 0, s, f->rev.elem,
+                           (const int32_t *)f->rev.elem_arc, f->rev.n_elem, arc_score_dev);
+    }
+    if (final_score_dev) {
+        hipLaunchKernelGGL(copy_f32, dim3(grid_for(f->Q, 256)), dim3(256), 0, s, f->final_score, final_score_dev,
+                           (int64_t)f->Q);
+        hipLaunchKernelGGL(final_max_kernel, dim3(1), dim3(1024), 0, s, (const float *)f->final_score, f->Q,
+                           f->final_max);
+    }
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+void wfst_fst_destroy(wfst_fst *f) { free_fst(f); }
+
+int wfst_fst_get_info(const wfst_fst *f, wfst_fst_info *info)
+{
+    if (!f || !info) return set_err(WFST_EINVAL, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->num_states = f->Q;
+    info->num_ilabels = f->M;
+    info->start = f->start;
+    info->chunk_arcs = f->chunk;
+    info->num_arcs = f->A;
+    info->fwd_elements = f->fwd.n_elem;
+    info->rev_elements = f->rev.n_elem;
+    info->fwd_segments = f->fwd.n_seg;
+    info->rev_segments = f->rev.n_seg;
+    info->fwd_slices = f->fwd.n_slice;
+    info->rev_slices = f->rev.n_slice;
+    info->max_fwd_segments_per_label = f->fwd.max_segs;
+    info->max_rev_segments_per_label = f->rev.max_segs;
+    info->max_fwd_slots_per_label = f->fwd.max_slots;
+    info->max_rev_slots_per_label = f->rev.max_slots;
+    info->device_bytes = f->bytes;
+    return WFST_OK;
+}
+
+int wfst_viterbi(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                 const int32_t *tokens, float *best_score, int32_t *best_arcs, int32_t *best_olabels,
+                 int32_t *status, void *stream)
+{
+    TRY(check_batch(fc, batch, num_tokens, offsets, tokens));
+    if (batch == 0) return WFST_OK;
+    if (!best_score || !status || (num_tokens > 0 && !best_arcs)) return set_err(WFST_EINVAL, "NULL output");
+    if (best_olabels && !fc->olabel) return set_err(WFST_EINVAL, "FST was created without olabels");
+    wfst_fst *f = const_cast<wfst_fst *>(fc);  // the workspace is mutable state of the FST
+    hipStream_t s = as_stream(stream);
+    const int64_t N = num_tokens;
+    int32_t *order, *counters, *path_tmp;
+    int64_t *tok_off, *tiles;
+    TRY(ensure_t(f->ws[W_ORDER], batch, s, &order));
+    TRY(ensure_t(f->ws[W_TOKOFF], N, s, &tok_off));
+    TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(N), s, &tiles));
+    TRY(ensure_t(f->ws[W_COUNTERS], C_COUNT, s, &counters));
+    TRY(ensure_t(f->ws[W_PATH], N, s, &path_tmp));
+    int64_t *dev_total = reinterpret_cast<int64_t *>(counters + C_TOTAL);
+    Plan p;
+    TRY(make_plan(f, s, batch, N, offsets, tokens, order, tok_off, tiles, dev_total, kBoundCapBytes / 8, p));
+    int2 *bp;
+    TRY(ensure_t(f->ws[W_BP], p.total, s, &bp));
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
+    const BatchView bv = make_view(f, batch, N, offsets, tokens, order, tok_off, counters + C_QUEUE, status);
+    int rc;
+    DISPATCH_NT(rc, f->nt, launch_viterbi, f, s, bv, bp, path_tmp, best_score, best_arcs, best_olabels)
+    return rc;
+}
+
+int wfst_forward(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                 const int32_t *tokens, float *log_z, int32_t *status, wfst_tape **tape_out, void *stream)
+{
+    TRY(check_batch(fc, batch, num_tokens, offsets, tokens));
+    if (!tape_out) return set_err(WFST_EINVAL, "tape_out is NULL");
+    *tape_out = nullptr;
+    if (batch > 0 && (!log_z || !status)) return set_err(WFST_EINVAL, "NULL output");
+    wfst_fst *f = const_cast<wfst_fst *>(fc);
+    hipStream_t s = as_stream(stream);
+    const int64_t N = num_tokens;
+    TapeBufs *tb;
+    if (!f->tape_pool.empty()) {
+        tb = f->tape_pool.back();
+        f->tape_pool.pop_back();
+    } else {
+        tb = new TapeBufs();
+    }
+    wfst_tape *t = new wfst_tape();
+    t->fst = f;
+    t->B = batch;
+    t->N = N;
+    t->offsets = offsets;
+    t->tokens = tokens;
+    t->status = status;
+    t->bufs = tb;
+    int rc = WFST_OK;
+    if (batch > 0) {
+        int32_t *counters;
+        int64_t *tiles, *dev_total;
+        rc = ensure_t(tb->order, batch, s, &t->order);
+        if (rc == WFST_OK) rc = ensure_t(tb->tok_off, N, s, &t->tok_off);
+        if (rc == WFST_OK) rc = ensure_t(tb->tiles, scan_tiles_for(N), s, &tiles);
+        if (rc == WFST_OK) rc = ensure_t(tb->total, 1, s, &dev_total);
+        if (rc == WFST_OK) rc = ensure_t(f->ws[W_COUNTERS], C_COUNT, s, &counters);
+        Plan p;
+        if (rc == WFST_OK)
+            rc = make_plan(f, s, batch, N, offsets, tokens, t->order, t->tok_off, tiles, dev_total,
+                           kBoundCapBytes / 4, p);
+        if (rc == WFST_OK) {
+            t->total = p.total;
+            rc = ensure_t(tb->alpha, p.total, s, &t->alpha);
+        }
+        if (rc == WFST_OK) rc = ensure_t(tb->a_max, N, s, &t->a_max);
+        if (rc == WFST_OK) rc = ensure_t(tb->a_log, N, s, &t->a_log);
+        if (rc == WFST_OK) rc = ensure_t(tb->log_z, batch, s, &t->log_z);
+        if (rc == WFST_OK) {
+            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
+            const BatchView bv =
+                make_view(f, batch, N, offsets, tokens, t->order, t->tok_off, counters + C_QUEUE, status);
+            TapeView tp;
+            tp.alpha = t->alpha;
+            tp.a_max = t->a_max;
+            tp.a_log = t->a_log;
+            tp.log_z = t->log_z;
+            DISPATCH_NT(rc, f->nt, launch_forward, f, s, bv, tp, log_z)
+        }
+    }
+    if (rc != WFST_OK) {
+        wfst_tape_free(t);
+        return rc;
+    }
+    *tape_out = t;
+    return WFST_OK;
+}
+
+void wfst_tape_free(wfst_tape *t)
+{
+    if (!t) return;
+    if (t->fst && t->bufs) const_cast<wfst_fst *>(t->fst)->tape_pool.push_back(t->bufs);
+    delete t;
+}
+
+int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_log_z, float *grad_arc_score,
+                  float *grad_final, void *stream)
+{
+    if (!fc || !tape) return set_err(WFST_EINVAL, "NULL fst or tape");
+    if (tape->fst != fc) return set_err(WFST_EINVAL, "tape belongs to another FST");
+    if (!grad_arc_score && fc->A > 0) return set_err(WFST_EINVAL, "grad_arc_score is NULL");
+    if (grad_final) return set_err(WFST_EUNSUPPORTED, "grad_final is not supported by this build");
+    wfst_fst *f = const_cast<wfst_fst *>(fc);
+    hipStream_t s = as_stream(stream);
+    if (f->A > 0)
+        hipLaunchKernelGGL(fill_f32, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s, grad_arc_score, f->A, 0.0f);
+    const int32_t B = tape->B;
+    const int64_t N = tape->N;
+    if (B == 0 || N == 0) {
+        HIP_OK(hipGetLastError());
+        return WFST_OK;
+    }
+    TapeView tp;
+    tp.alpha = tape->alpha;
+    tp.a_max = tape->a_max;
+    tp.a_log = tape->a_log;
+    tp.log_z = tape->log_z;
+    int32_t *counters;
+    TRY(ensure_t(f->ws[W_BETA], tape->total, s, &tp.beta));
+    TRY(ensure_t(f->ws[W_BMAX], N, s, &tp.b_max));
+    TRY(ensure_t(f->ws[W_BLOG], N, s, &tp.b_log));
+    TRY(ensure_t(f->ws[W_LZB], B, s, &tp.log_z_bwd));
+    TRY(ensure_t(f->ws[W_COUNTERS], C_COUNT, s, &counters));
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
+    const BatchView bv = make_view(f, B, N, tape->offsets, tape->tokens, tape->order, tape->tok_off,
+                                   counters + C_QUEUE, tape->status);
+    int rc;
+    DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp)
+    if (rc != WFST_OK) return rc;
+
+    // group the visits (token positions) by input label, stable in position
+    const int32_t V = 64;
+    int32_t *tok_sent, *visits, *skeys, *grp_lo, *grp_n, *nip, *item_base, *item_slot;
+    TRY(ensure_t(f->ws[W_TOKSENT], N, s, &tok_sent));
+    TRY(sort_visits(f, s, N, tape->tokens, tape->offsets, B, &visits, &skeys, tok_sent));
+    TRY(ensure_t(f->ws[W_GRPLO], f->M, s, &grp_lo));
+    TRY(ensure_t(f->ws[W_GRPN], f->M, s, &grp_n));
+    TRY(ensure_t(f->ws[W_NIP], f->M, s, &nip));
+    TRY(ensure_t(f->ws[W_ITEMBASE], f->M, s, &item_base));
+    const int64_t items_bound = N / V + std::min<int64_t>(f->M, N) + 1;
+    CountItem *items;
+    TRY(ensure_t(f->ws[W_ITEMS], items_bound, s, &items));
+    TRY(ensure_t(f->ws[W_ITEMSLOT], items_bound, s, &item_slot));
+    const int64_t split_bound = 2 * (N / V) + 2;
+    float *partial;
+    TRY(ensure_t(f->ws[W_PARTIAL], split_bound * (int64_t)std::max(f->fwd.max_elems, 1), s, &partial));
+    int64_t *tiles;
+    TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(std::max<int64_t>(f->M, 256 * ((N + kSortTile - 1) / kSortTile))),
+                 s, &tiles));
+    hipLaunchKernelGGL(label_groups, dim3(grid_for(f->M, 256)), dim3(256), 0, s, (const int32_t *)skeys, N, f->M, V,
+                       grp_lo, grp_n, nip);
+    ScanSource src;
+    src.i32 = nip;
+    TRY(launch_scan<int32_t>(s, src, f->M, tiles, item_base, nullptr));
+    hipLaunchKernelGGL(label_items, dim3(grid_for(f->M, 256)), dim3(256), 0, s, (const int32_t *)grp_lo,
+                       (const int32_t *)grp_n, (const int32_t *)nip, (const int32_t *)item_base, f->M, V, items,
+                       counters + C_NITEMS);
+    const int ch = f->chunk;
+    if (ch <= 4)
+        rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent, grad_log_z,
+                                 grad_arc_score, partial, item_slot, counters + C_SLOTS);
+    else if (ch <= 8)
+        rc = launch_counts_ch<8>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent, grad_log_z,
+                                 grad_arc_score, partial, item_slot, counters + C_SLOTS);
+    else if (ch <= 16)
+        rc = launch_counts_ch<16>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
+                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS);
+    else if (ch <= 32)
+        rc = launch_counts_ch<32>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
+                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS);
+    else
+        rc = launch_counts_ch<64>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
+                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS);
+    if (rc != WFST_OK) return rc;
+    hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(items_bound, 1, 4096)), dim3(256), 0, s, f->fwd,
+                       (const CountItem *)items, (const int32_t *)(counters + C_NITEMS), (const int32_t *)item_slot,
+                       (const float *)partial, grad_arc_score);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+int wfst_forward_backward(const wfst_fst *f, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                          const int32_t *tokens, float *log_z, float *arc_posterior, float *final_posterior,
+                          int32_t *status, void *stream)
+{
+    wfst_tape *t = nullptr;
+    TRY(wfst_forward(f, batch, num_tokens, offsets, tokens, log_z, status, &t, stream));
+    int rc = wfst_backward(f, t, nullptr, arc_posterior, final_posterior, stream);
+    wfst_tape_free(t);
+    return rc;
+}
+
+}  // extern "C"

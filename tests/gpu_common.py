@@ -1,0 +1,61 @@
+"""Helpers shared by the GPU parity tests (they call the HIP path through the C ABI)."""
+import sys
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_viterbi(fst_dev, batch, olabels=False):
+    import torch
+    import paper_1701_03038_amd as wf
+    out = wf.viterbi(fst_dev, batch.offsets, batch.tokens, olabels=olabels)
+    torch.cuda.synchronize()
+    return tuple(x.cpu().numpy() for x in out)
+
+
+def assert_viterbi_parity(fst, batch, fst_dev, ctx=""):
+    """Bit-exact best scores, identical paths and statuses."""
+    score, arcs, status = run_viterbi(fst_dev, batch)
+    osc, oarcs, ost = oracle.viterbi(fst, batch)
+    np.testing.assert_array_equal(status, ost, err_msg=f"status {ctx}")
+    bad = np.nonzero(score.view(np.uint32) != osc.view(np.uint32))[0]
+    assert bad.size == 0, f"{ctx}: {bad.size} scores differ, first b={bad[:5]} gpu={score[bad[:5]]} oracle={osc[bad[:5]]}"
+    diff = np.nonzero(arcs != oarcs)[0]
+    assert diff.size == 0, f"{ctx}: {diff.size} path arcs differ, first token {diff[:5]}"
+    return score, arcs, status
+
+
+def visits_per_arc(fst, batch):
+    """n_k: number of (sentence, step) visits whose input symbol is arc k's label."""
+    cnt = np.bincount(batch.tokens, minlength=fst.num_ilabels)
+    return cnt[fst.ilabel].astype(np.float64)
+
+
+def assert_fb_parity(fst, batch, fst_dev, ctx="", per_sentence_tol=False):
+    """log Z within 1e-4 relative; batch-summed posteriors within 1e-5 per visit."""
+    import torch
+    import paper_1701_03038_amd as wf
+    lz, post, st = wf.forward_backward(fst_dev, batch.offsets, batch.tokens)
+    torch.cuda.synchronize()
+    lz, post, st = lz.cpu().numpy(), post.cpu().numpy(), st.cpu().numpy()
+    olz, opost, _, ost = oracle.forward_backward(fst, batch)
+    np.testing.assert_array_equal(st, ost, err_msg=f"status {ctx}")
+    ok = ost == oracle.ST_OK
+    assert np.all(lz[~ok] == -np.inf)
+    err = np.abs(lz[ok].astype(np.float64) - olz[ok])
+    tol = 1e-4 * np.maximum(1.0, np.abs(olz[ok]))
+    assert np.all(err <= tol), f"{ctx}: log Z max rel err {np.max(err / np.maximum(1, np.abs(olz[ok]))):.3g}"
+    n_k = visits_per_arc(fst, batch)
+    perr = np.abs(post.astype(np.float64) - opost)
+    bound = 1e-5 * np.maximum(1.0, n_k)
+    worst = np.argmax(perr / bound) if perr.size else 0
+    assert np.all(perr <= bound), (f"{ctx}: posterior err {perr[worst]:.3g} at arc {worst} "
+                                   f"(n_k={n_k[worst]}, gpu={post[worst]}, oracle={opost[worst]})")
+    assert not np.any(np.isnan(post))
+    return lz, post, st
