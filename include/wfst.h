@@ -112,6 +112,17 @@ void wfst_fst_destroy(wfst_fst *fst);
 
 int wfst_fst_get_info(const wfst_fst *fst, wfst_fst_info *info);
 
+/* Health bits of the FST's kernels (failure detection).  Every loop whose
+ * bound comes from device memory is checked; on inconsistent data a kernel
+ * stops that piece of work and sets a bit instead of running away:
+ *   1 queue overrun, 2 count work item out of range, 4 visit / token /
+ *   sentence index out of range, 8 partial-count slot out of range,
+ *   16 sort scatter out of range, 32 label grouping overflow.
+ * Bits are sticky across calls.  *flags (host) receives the word after the
+ * FST's work queued on `stream` has finished (the call synchronises the
+ * stream); clear != 0 resets the word afterwards.  0 means healthy. */
+int wfst_fst_health(const wfst_fst *fst, uint32_t *flags, int32_t clear, void *stream);
+
 /*
  * Viterbi decoding of a batch (paper, Algorithm 1 + section 5.1).
  * Outputs (caller-owned DEVICE memory):

@@ -59,7 +59,7 @@ class _Info(ctypes.Structure):
 
 
 EXPORTS = (
-    "wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_destroy", "wfst_fst_get_info",
+    "wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_destroy", "wfst_fst_get_info", "wfst_fst_health",
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host",
 )
@@ -81,6 +81,7 @@ def load_library(path: str | None = None):
     lib.wfst_fst_destroy.argtypes = [P]
     lib.wfst_fst_destroy.restype = None
     lib.wfst_fst_get_info.argtypes = [P, ctypes.POINTER(_Info)]
+    lib.wfst_fst_health.argtypes = [P, ctypes.POINTER(ctypes.c_uint32), i32, P]
     lib.wfst_viterbi.argtypes = [P, i32, i64, P, P, P, P, P, P, P]
     lib.wfst_forward.argtypes = [P, i32, i64, P, P, P, P, ctypes.POINTER(P), P]
     lib.wfst_backward.argtypes = [P, P, P, P, P, P]
@@ -90,7 +91,7 @@ def load_library(path: str | None = None):
     lib.wfst_last_error.argtypes = []
     lib.wfst_last_error.restype = ctypes.c_char_p
     lib.wfst_layout_host.argtypes = [i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
-    for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_viterbi",
+    for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health", "wfst_viterbi",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
@@ -173,6 +174,12 @@ class Fst:
         inf = _Info()
         _check(_lib.wfst_fst_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def health(self, clear: bool = False) -> int:
+        """Sticky health bits of the FST's kernels (0 = healthy); synchronises the stream."""
+        out = ctypes.c_uint32(0)
+        _check(_lib.wfst_fst_health(self.handle, ctypes.byref(out), int(clear), _stream()))
+        return int(out.value)
 
     def set_scores(self, arc_score, final_score=None):
         """New scores from device float32 tensors (arc-id order), async on the current stream."""

@@ -31,6 +31,23 @@ struct BatchView {
     const int64_t *tok_off = nullptr;  // [N] compact per-step storage offsets (prefix of segment counts)
     int32_t *queue = nullptr;          // work-queue head
     int32_t *status = nullptr;         // [B]
+    uint32_t *health = nullptr;        // sticky WFST_HEALTH_* bits (see below)
+};
+
+// Health bits: a kernel that finds device data outside what its loops may
+// trust stops that piece of work and records why, instead of running away.
+enum HealthBit : uint32_t {
+    H_QUEUE = 1u,      // a persistent workgroup popped more items than exist
+    H_ITEM = 2u,       // a count work item or the item count is out of range
+    H_VISIT = 4u,      // a visit, token or sentence index is out of range
+    H_SLOT = 8u,       // a split-label partial slot is beyond its buffer
+    H_SCATTER = 16u,   // a sort scatter position is out of range
+    H_GROUP = 32u,     // label grouping produced more items than reserved
+};
+
+// Capacities the count kernels check their device-side inputs against.
+struct CountCaps {
+    int32_t items_cap = 0, slot_cap = 0, V = 0;
 };
 
 // The forward-backward tape (compact: one value per (token, forward segment)).

@@ -174,7 +174,8 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const int32_t *__r
                                                               int shift, int64_t ntiles,
                                                               const int64_t *__restrict__ offs,
                                                               int32_t *__restrict__ keys_out,
-                                                              int32_t *__restrict__ vals_out)
+                                                              int32_t *__restrict__ vals_out,
+                                                              uint32_t *__restrict__ health)
 {
     constexpr int NW = kSortThreads / 64;
     __shared__ int wcnt[NW][256];
@@ -220,6 +221,10 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const int32_t *__r
     for (int k = 0; k < kSortItems; ++k) {
         if (dg[k] < 0) continue;
         const int64_t pos = offs[(int64_t)dg[k] * ntiles + blockIdx.x] + wcnt[wave][dg[k]] + rank[k];
+        if (pos < 0 || pos >= n) {
+            atomicOr(health, H_SCATTER);
+            continue;
+        }
         keys_out[pos] = kv[k];
         vals_out[pos] = vv[k];
     }

@@ -146,12 +146,16 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     const int lane = tid & 63;
     const int wave = wave_uniform(tid >> 6);
 
-    for (;;) {
+    for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(bv.queue, 1);
         __syncthreads();
         const int item = s_item;
         __syncthreads();
         if (item >= bv.B) break;
+        if (item < 0 || pops > bv.B) {
+            if (tid == 0) atomicOr(bv.health, H_QUEUE);
+            break;
+        }
         const int b = bv.order[item];
         int o0, o1;
         const int st = check_sentence<NT>(bv, b, o0, o1);
@@ -384,12 +388,16 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     const int lane = tid & 63;
     const int wave = wave_uniform(tid >> 6);
 
-    for (;;) {
+    for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(bv.queue, 1);
         __syncthreads();
         const int item = s_item;
         __syncthreads();
         if (item >= bv.B) break;
+        if (item < 0 || pops > bv.B) {
+            if (tid == 0) atomicOr(bv.health, H_QUEUE);
+            break;
+        }
         const int b = bv.order[item];
         int o0, o1;
         const int st = check_sentence<NT>(bv, b, o0, o1);
@@ -495,12 +503,16 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     const int wave = wave_uniform(tid >> 6);
     const float fmax0 = *final_max;
 
-    for (;;) {
+    for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(bv.queue, 1);
         __syncthreads();
         const int item = s_item;
         __syncthreads();
         if (item >= bv.B) break;
+        if (item < 0 || pops > bv.B) {
+            if (tid == 0) atomicOr(bv.health, H_QUEUE);
+            break;
+        }
         const int b = bv.order[item];
         if (bv.status[b] != WFST_STATUS_OK) continue;
         const int o0 = bv.offsets[b], o1 = bv.offsets[b + 1];
@@ -592,7 +604,7 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
               const int32_t *__restrict__ visits, const int32_t *__restrict__ tok_sent,
               const float *__restrict__ grad_log_z, float *__restrict__ grad,
               float *__restrict__ partial, int32_t *__restrict__ item_slot,
-              int32_t *__restrict__ slot_counter)
+              int32_t *__restrict__ slot_counter, CountCaps caps)
 {
     constexpr int NW = NT / 64;
     constexpr int KPP = 64 / CH;
@@ -610,9 +622,18 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
         den0[q] = CEnt{WFST_NINF, -1};
         den1[q] = CEnt{WFST_NINF, -1};
     }
-    const int nit = *n_items;
+    int nit = *n_items;
+    if (nit < 0 || nit > caps.items_cap) {
+        if (blockIdx.x == 0 && tid == 0) atomicOr(bv.health, H_ITEM);
+        nit = 0;
+    }
     for (int it = blockIdx.x; it < nit; it += gridDim.x) {
         const CountItem ci = items[it];
+        if (ci.first < 0 || ci.last < ci.first || (int64_t)ci.last > bv.N || ci.last - ci.first > caps.V ||
+            ci.label < 0 || ci.label >= bv.M) {
+            if (tid == 0) atomicOr(bv.health, H_ITEM);
+            continue;
+        }
         const LabelInfo li = fl.label[ci.label];
         __syncthreads();
         for (int j = tid; j < li.n_multi; j += NT) {
@@ -624,7 +645,11 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
             item_slot[it] = s_slot;
         }
         __syncthreads();
-        const int slot = ci.split ? s_slot : -1;
+        int slot = ci.split ? s_slot : -1;
+        if (ci.split && (slot < 0 || slot >= caps.slot_cap)) {
+            if (tid == 0) atomicOr(bv.health, H_SLOT);
+            slot = -2;  // compute, write nothing
+        }
         const int passes = (li.n_slices + NW * KPP - 1) / (NW * KPP);
         for (int pass = 0; pass < passes; ++pass) {
             __syncthreads();  // the previous pass may still read either density buffer
@@ -633,8 +658,15 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
             for (int r = 0; r < MAXR; ++r) acc[r] = 0.0f;
             for (int v = ci.first; v < ci.last; ++v) {
                 const int i = visits[v];
-                const int b = tok_sent[i];
-                const bool live = bv.status[b] == WFST_STATUS_OK;
+                bool live = i >= 0 && (int64_t)i < bv.N;
+                const int b = live ? tok_sent[i] : 0;
+                live = live && b >= 0 && b < bv.B;
+                if (live) {
+                    const int o0 = bv.offsets[b], o1 = bv.offsets[b + 1];
+                    live = i >= o0 && i < o1 && bv.tokens[i] == ci.label;
+                }
+                if (!live && tid == 0) atomicOr(bv.health, H_VISIT);
+                live = live && bv.status[b] == WFST_STATUS_OK;
                 CEnt *den = (v & 1) ? den1 : den0;
                 float o = 0.0f, g = 1.0f;
                 int t = 0;
@@ -693,10 +725,10 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
                             if (r < si.height) {
                                 const int pos = si.base + r * si.width + lane;
                                 const float val = acc[k * CH + r];
-                                if (slot < 0) {
+                                if (slot == -1) {
                                     const int arc = fl.elem_arc[pos];
                                     if (arc >= 0) grad[arc] = val;
-                                } else {
+                                } else if (slot >= 0) {
                                     partial[(int64_t)slot * fl.max_elems + (pos - li.elem_first)] = val;
                                 }
                             }
@@ -713,16 +745,23 @@ template <int NT>
 __global__ void __launch_bounds__(NT)
 counts_fixup(DevLayout fl, const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
              const int32_t *__restrict__ item_slot, const float *__restrict__ partial,
-             float *__restrict__ grad)
+             float *__restrict__ grad, CountCaps caps, int32_t M, uint32_t *health)
 {
-    const int nit = *n_items;
+    int nit = *n_items;
+    if (nit < 0 || nit > caps.items_cap) nit = 0;  // the count kernel already flagged it
     for (int it = blockIdx.x; it < nit; it += gridDim.x) {
         const CountItem ci = items[it];
-        if (!ci.split) continue;
+        if (!ci.split || ci.label < 0 || ci.label >= M) continue;
         if (it > 0 && items[it - 1].label == ci.label) continue;  // first item of the label only
         int last = it;
         while (last + 1 < nit && items[last + 1].label == ci.label) ++last;
         const LabelInfo li = fl.label[ci.label];
+        bool ok = true;
+        for (int k = it; k <= last; ++k) ok = ok && item_slot[k] >= 0 && item_slot[k] < caps.slot_cap;
+        if (!ok) {
+            if (threadIdx.x == 0) atomicOr(health, H_SLOT);
+            continue;
+        }
         for (int e = threadIdx.x; e < li.n_elems; e += NT) {
             float s = 0.0f;
             for (int k = it; k <= last; ++k) s += partial[(int64_t)item_slot[k] * fl.max_elems + e];
@@ -814,11 +853,16 @@ __global__ void label_groups(const int32_t *__restrict__ skeys, int64_t N, int32
 __global__ void label_items(const int32_t *__restrict__ grp_lo, const int32_t *__restrict__ grp_n,
                             const int32_t *__restrict__ n_items_per_label,
                             const int32_t *__restrict__ item_base, int32_t M, int32_t V,
-                            CountItem *__restrict__ items, int32_t *__restrict__ n_items)
+                            CountItem *__restrict__ items, int32_t *__restrict__ n_items, int32_t items_cap,
+                            uint32_t *__restrict__ health)
 {
     for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < M; a += gridDim.x * blockDim.x) {
         const int k = n_items_per_label[a];
         const int base = item_base[a];
+        if (base < 0 || k < 0 || base + k > items_cap) {
+            atomicOr(health, H_GROUP);
+            continue;
+        }
         for (int x = 0; x < k; ++x) {
             const int f = grp_lo[a] + x * V;
             const int l = min(grp_lo[a] + grp_n[a], f + V);

@@ -110,6 +110,7 @@ struct wfst_fst {
     float *final_score = nullptr;
     float *final_max = nullptr;
     int32_t *olabel = nullptr;
+    uint32_t *health = nullptr;  // sticky health bits of the kernels (see wfst_fst_health)
     int64_t bytes = 0;
     int cu_count = 0;
     size_t max_lds = 0;
@@ -324,14 +325,14 @@ template <int CH>
 int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
                      const CountItem *items, const int32_t *n_items, int64_t items_bound, const int32_t *visits,
                      const int32_t *tok_sent, const float *g, float *grad, float *partial, int32_t *item_slot,
-                     int32_t *slot_counter)
+                     int32_t *slot_counter, CountCaps caps)
 {
     constexpr int NT = 256;
     const size_t lds = lds_counts(f);
     int grid = 0;
     TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
     hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start, bv, tp,
-                       items, n_items, visits, tok_sent, g, grad, partial, item_slot, slot_counter);
+                       items, n_items, visits, tok_sent, g, grad, partial, item_slot, slot_counter, caps);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -358,6 +359,7 @@ BatchView make_view(const wfst_fst *f, int32_t B, int64_t N, const int32_t *offs
     bv.tok_off = tok_off;
     bv.queue = queue;
     bv.status = status;
+    bv.health = f->health;
     return bv;
 }
 
@@ -388,7 +390,7 @@ int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, co
         src.i64 = hist;
         TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
         hipLaunchKernelGGL(radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
-                           (const int32_t *)v0, N, shift, ntiles, (const int64_t *)hist, k1, v1);
+                           (const int32_t *)v0, N, shift, ntiles, (const int64_t *)hist, k1, v1, f->health);
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
@@ -531,6 +533,9 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         }
         if (rc == WFST_OK) rc = dev_upload(f, &f->final_score, final_score, num_states, s);
         if (rc == WFST_OK) rc = dev_upload<float>(f, &f->final_max, nullptr, 1, s);
+        if (rc == WFST_OK) rc = dev_upload<uint32_t>(f, &f->health, nullptr, 1, s);
+        if (rc == WFST_OK)
+            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t *>(f->health), (int64_t)1, 0);
         if (rc == WFST_OK && olabel) rc = dev_upload(f, &f->olabel, olabel, num_arcs, s);
         if (rc == WFST_OK) {
             hipLaunchKernelGGL(final_max_kernel, dim3(1), dim3(1024), 0, s, (const float *)f->final_score, f->Q,
@@ -572,6 +577,19 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
 }
 
 void wfst_fst_destroy(wfst_fst *f) { free_fst(f); }
+
+int wfst_fst_health(const wfst_fst *f, uint32_t *flags, int32_t clear, void *stream)
+{
+    if (!f || !flags) return set_err(WFST_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    HIP_OK(hipMemcpyAsync(flags, f->health, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (clear) {
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t *>(f->health), (int64_t)1, 0);
+        HIP_OK(hipGetLastError());
+    }
+    return WFST_OK;
+}
 
 int wfst_fst_get_info(const wfst_fst *f, wfst_fst_info *info)
 {
@@ -759,27 +777,31 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     TRY(launch_scan<int32_t>(s, src, f->M, tiles, item_base, nullptr));
     hipLaunchKernelGGL(label_items, dim3(grid_for(f->M, 256)), dim3(256), 0, s, (const int32_t *)grp_lo,
                        (const int32_t *)grp_n, (const int32_t *)nip, (const int32_t *)item_base, f->M, V, items,
-                       counters + C_NITEMS);
+                       counters + C_NITEMS, (int32_t)items_bound, f->health);
+    CountCaps caps;
+    caps.items_cap = (int32_t)items_bound;
+    caps.slot_cap = (int32_t)split_bound;
+    caps.V = V;
     const int ch = f->chunk;
     if (ch <= 4)
         rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent, grad_log_z,
-                                 grad_arc_score, partial, item_slot, counters + C_SLOTS);
+                                 grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 8)
         rc = launch_counts_ch<8>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent, grad_log_z,
-                                 grad_arc_score, partial, item_slot, counters + C_SLOTS);
+                                 grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 16)
         rc = launch_counts_ch<16>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
-                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS);
+                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 32)
         rc = launch_counts_ch<32>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
-                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS);
+                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
     else
         rc = launch_counts_ch<64>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
-                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS);
+                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
     if (rc != WFST_OK) return rc;
     hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(items_bound, 1, 4096)), dim3(256), 0, s, f->fwd,
                        (const CountItem *)items, (const int32_t *)(counters + C_NITEMS), (const int32_t *)item_slot,
-                       (const float *)partial, grad_arc_score);
+                       (const float *)partial, grad_arc_score, caps, f->M, f->health);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }

@@ -16,6 +16,7 @@ def run_viterbi(fst_dev, batch, olabels=False):
     import paper_1701_03038_amd as wf
     out = wf.viterbi(fst_dev, batch.offsets, batch.tokens, olabels=olabels)
     torch.cuda.synchronize()
+    assert fst_dev.health() == 0, f"kernel health flags {fst_dev.health():#x}"
     return tuple(x.cpu().numpy() for x in out)
 
 
@@ -43,6 +44,7 @@ def assert_fb_parity(fst, batch, fst_dev, ctx="", per_sentence_tol=False):
     import paper_1701_03038_amd as wf
     lz, post, st = wf.forward_backward(fst_dev, batch.offsets, batch.tokens)
     torch.cuda.synchronize()
+    assert fst_dev.health() == 0, f"kernel health flags {fst_dev.health():#x}"
     lz, post, st = lz.cpu().numpy(), post.cpu().numpy(), st.cpu().numpy()
     olz, opost, _, ost = oracle.forward_backward(fst, batch)
     np.testing.assert_array_equal(st, ost, err_msg=f"status {ctx}")
