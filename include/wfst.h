@@ -112,6 +112,25 @@ void wfst_fst_destroy(wfst_fst *fst);
 
 int wfst_fst_get_info(const wfst_fst *fst, wfst_fst_info *info);
 
+/* Per input label (host int32[num_ilabels] each, any may be NULL): number of
+ * arcs, of (label, destination) segments and of (label, source) segments. */
+int wfst_fst_label_stats(const wfst_fst *fst, int32_t *arcs, int32_t *fwd_segments, int32_t *rev_segments);
+
+/* Per-kernel timing for benchmarks.  While enabled, every launch of the
+ * library's main kernels is bracketed by HIP events on the call's stream.
+ * wfst_fst_profile_read waits for the recorded events and returns, per kernel
+ * kind (WFST_KERNEL_*), the summed elapsed milliseconds and the number of
+ * launches (host arrays of WFST_KERNEL_COUNT); reset != 0 forgets them. */
+#define WFST_KERNEL_VITERBI 0    /* Viterbi sweep incl. final state and backtrace */
+#define WFST_KERNEL_FORWARD 1    /* forward (alpha) sweep incl. log Z */
+#define WFST_KERNEL_BACKWARD 2   /* backward (beta) sweep */
+#define WFST_KERNEL_COUNTS 3     /* expected counts by label group */
+#define WFST_KERNEL_SCORES 4     /* score scatter of wfst_fst_set_scores (both layouts) */
+#define WFST_KERNEL_GRAD_FILL 5  /* zero fill of the gradient */
+#define WFST_KERNEL_COUNT 6
+int wfst_fst_profile(wfst_fst *fst, int32_t enable);
+int wfst_fst_profile_read(wfst_fst *fst, double *ms, int64_t *launches, int32_t reset);
+
 /* Health bits of the FST's kernels (failure detection).  Every loop whose
  * bound comes from device memory is checked; on inconsistent data a kernel
  * stops that piece of work and sets a bit instead of running away:

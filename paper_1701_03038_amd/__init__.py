@@ -60,6 +60,7 @@ class _Info(ctypes.Structure):
 
 EXPORTS = (
     "wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_destroy", "wfst_fst_get_info", "wfst_fst_health",
+    "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats",
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host",
 )
@@ -82,6 +83,9 @@ def load_library(path: str | None = None):
     lib.wfst_fst_destroy.restype = None
     lib.wfst_fst_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.wfst_fst_health.argtypes = [P, ctypes.POINTER(ctypes.c_uint32), i32, P]
+    lib.wfst_fst_profile.argtypes = [P, i32]
+    lib.wfst_fst_label_stats.argtypes = [P, P, P, P]
+    lib.wfst_fst_profile_read.argtypes = [P, P, P, i32]
     lib.wfst_viterbi.argtypes = [P, i32, i64, P, P, P, P, P, P, P]
     lib.wfst_forward.argtypes = [P, i32, i64, P, P, P, P, ctypes.POINTER(P), P]
     lib.wfst_backward.argtypes = [P, P, P, P, P, P]
@@ -91,7 +95,8 @@ def load_library(path: str | None = None):
     lib.wfst_last_error.argtypes = []
     lib.wfst_last_error.restype = ctypes.c_char_p
     lib.wfst_layout_host.argtypes = [i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
-    for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health", "wfst_viterbi",
+    for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health",
+                 "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats", "wfst_viterbi",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
@@ -174,6 +179,25 @@ class Fst:
         inf = _Info()
         _check(_lib.wfst_fst_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    KERNELS = ("viterbi", "forward", "backward", "counts", "scores", "grad_fill")
+
+    def label_stats(self):
+        """(arcs, forward segments, reverse segments) per input label, int32 numpy arrays."""
+        out = [np.zeros(self.num_ilabels, np.int32) for _ in range(3)]
+        _check(_lib.wfst_fst_label_stats(self.handle, *(_np_ptr(a) for a in out)))
+        return tuple(out)
+
+    def profile(self, enable: bool = True):
+        """Bracket the main kernels of later calls with HIP events (for benchmarks)."""
+        _check(_lib.wfst_fst_profile(self.handle, int(enable)))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{kernel: (total ms, launches)} for the calls made while profiling."""
+        ms = np.zeros(len(self.KERNELS), np.float64)
+        n = np.zeros(len(self.KERNELS), np.int64)
+        _check(_lib.wfst_fst_profile_read(self.handle, _np_ptr(ms), _np_ptr(n), int(reset)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS)}
 
     def health(self, clear: bool = False) -> int:
         """Sticky health bits of the FST's kernels (0 = healthy); synchronises the stream."""

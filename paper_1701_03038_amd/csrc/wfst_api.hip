@@ -117,6 +117,14 @@ struct wfst_fst {
     std::vector<void *> allocs;
     Buf ws[W_NUM];
     std::vector<TapeBufs *> tape_pool;
+    // per-kernel timing (wfst_fst_profile): event pairs recorded around the main kernels
+    std::vector<int32_t> label_arcs, label_fwd_segs, label_rev_segs;  // host copies for reporting
+    bool prof = false;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks, spare;
 };
 
 struct wfst_tape {
@@ -186,9 +194,36 @@ void free_fst(wfst_fst *f)
             free_buf(*b);
         delete t;
     }
+    for (auto &m : f->marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
+    for (auto &m : f->spare) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
     if (other) (void)hipSetDevice(cur);
     delete f;
 }
+
+// Brackets one main-kernel launch with timing events when profiling is on.
+struct ProfScope {
+    wfst_fst *f;
+    hipStream_t s;
+    int kind;
+    wfst_fst::Mark m{};
+    bool on = false;
+    ProfScope(const wfst_fst *fc, hipStream_t st, int k) : f(const_cast<wfst_fst *>(fc)), s(st), kind(k)
+    {
+        if (!f->prof) return;
+        if (!f->spare.empty()) {
+            m = f->spare.back();
+            f->spare.pop_back();
+        } else if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) {
+            return;
+        }
+        m.kind = kind;
+        on = hipEventRecord(m.a, s) == hipSuccess;
+    }
+    ~ProfScope()
+    {
+        if (on && hipEventRecord(m.b, s) == hipSuccess) f->marks.push_back(m);
+    }
+};
 
 // LDS bytes of each kernel for this FST.
 size_t lds_viterbi(const wfst_fst *f)
@@ -290,6 +325,7 @@ int launch_viterbi(const wfst_fst *f, hipStream_t s, const BatchView &bv, int2 *
     const size_t lds = lds_viterbi(f);
     int grid = 0;
     TRY(persistent_grid(f, viterbi_sweep<NT>, NT, lds, bv.B, &grid));
+    ProfScope prof(f, s, WFST_KERNEL_VITERBI);
     hipLaunchKernelGGL((viterbi_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start,
                        (const float *)f->final_score, bv, bp, path_tmp, best_score, best_arcs, best_olabels,
                        (const int32_t *)f->olabel);
@@ -303,6 +339,7 @@ int launch_forward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const 
     const size_t lds = lds_lse(f, f->fwd);
     int grid = 0;
     TRY(persistent_grid(f, forward_sweep<NT>, NT, lds, bv.B, &grid));
+    ProfScope prof(f, s, WFST_KERNEL_FORWARD);
     hipLaunchKernelGGL((forward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start,
                        (const float *)f->final_score, bv, tp, log_z);
     HIP_OK(hipGetLastError());
@@ -315,6 +352,7 @@ int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const
     const size_t lds = lds_lse(f, f->rev);
     int grid = 0;
     TRY(persistent_grid(f, backward_sweep<NT>, NT, lds, bv.B, &grid));
+    ProfScope prof(f, s, WFST_KERNEL_BACKWARD);
     hipLaunchKernelGGL((backward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start,
                        (const float *)f->final_score, (const float *)f->final_max, bv, tp);
     HIP_OK(hipGetLastError());
@@ -331,6 +369,7 @@ int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, cons
     const size_t lds = lds_counts(f);
     int grid = 0;
     TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
+    ProfScope prof(f, s, WFST_KERNEL_COUNTS);
     hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start, bv, tp,
                        items, n_items, visits, tok_sent, g, grad, partial, item_slot, slot_counter, caps);
     HIP_OK(hipGetLastError());
@@ -521,6 +560,12 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
             HostLayout h;
             rc = build_layout(num_states, num_ilabels, num_arcs, src, dst, ilabel, arc_score, 0, L, h, err);
             if (rc != WFST_OK) rc = set_err(rc, err);
+            if (rc == WFST_OK) {
+                f->label_arcs.assign((size_t)num_ilabels, 0);
+                f->label_fwd_segs.resize((size_t)num_ilabels);
+                for (int32_t a = 0; a < num_ilabels; ++a) f->label_fwd_segs[(size_t)a] = h.label[(size_t)a].n_segs;
+                for (int64_t k = 0; k < num_arcs; ++k) f->label_arcs[(size_t)ilabel[k]] += 1;
+            }
             if (rc == WFST_OK) rc = upload_layout(f, h, f->fwd, s);
             if (rc == WFST_OK && hipStreamSynchronize(s) != hipSuccess) rc = set_err(WFST_EHIP, "upload failed");
         }
@@ -528,6 +573,10 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
             HostLayout h;
             rc = build_layout(num_states, num_ilabels, num_arcs, src, dst, ilabel, arc_score, 1, L, h, err);
             if (rc != WFST_OK) rc = set_err(rc, err);
+            if (rc == WFST_OK) {
+                f->label_rev_segs.resize((size_t)num_ilabels);
+                for (int32_t a = 0; a < num_ilabels; ++a) f->label_rev_segs[(size_t)a] = h.label[(size_t)a].n_segs;
+            }
             if (rc == WFST_OK) rc = upload_layout(f, h, f->rev, s);
             if (rc == WFST_OK && hipStreamSynchronize(s) != hipSuccess) rc = set_err(WFST_EHIP, "upload failed");
         }
@@ -561,6 +610,7 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
     if (!f) return set_err(WFST_EINVAL, "fst is NULL");
     hipStream_t s = as_stream(stream);
     if (arc_score_dev && f->A > 0) {
+        ProfScope prof(f, s, WFST_KERNEL_SCORES);
         hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->fwd.n_elem, 256, 8192)), dim3(256), 0, s, f->fwd.elem,
                            (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, arc_score_dev);
         hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->rev.n_elem, 256, 8192)), dim3(256), 0, s, f->rev.elem,
@@ -577,6 +627,46 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
 }
 
 void wfst_fst_destroy(wfst_fst *f) { free_fst(f); }
+
+int wfst_fst_label_stats(const wfst_fst *f, int32_t *arcs, int32_t *fwd_segments, int32_t *rev_segments)
+{
+    if (!f) return set_err(WFST_EINVAL, "fst is NULL");
+    const size_t n = (size_t)f->M * sizeof(int32_t);
+    if (arcs) std::memcpy(arcs, f->label_arcs.data(), n);
+    if (fwd_segments) std::memcpy(fwd_segments, f->label_fwd_segs.data(), n);
+    if (rev_segments) std::memcpy(rev_segments, f->label_rev_segs.data(), n);
+    return WFST_OK;
+}
+
+int wfst_fst_profile(wfst_fst *f, int32_t enable)
+{
+    if (!f) return set_err(WFST_EINVAL, "fst is NULL");
+    f->prof = enable != 0;
+    return WFST_OK;
+}
+
+int wfst_fst_profile_read(wfst_fst *f, double *ms, int64_t *launches, int32_t reset)
+{
+    if (!f || !ms || !launches) return set_err(WFST_EINVAL, "NULL argument");
+    for (int k = 0; k < WFST_KERNEL_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &m : f->marks) {
+        HIP_OK(hipEventSynchronize(m.b));
+        float t = 0.0f;
+        HIP_OK(hipEventElapsedTime(&t, m.a, m.b));
+        if (m.kind >= 0 && m.kind < WFST_KERNEL_COUNT) {
+            ms[m.kind] += t;
+            launches[m.kind] += 1;
+        }
+    }
+    if (reset) {
+        for (auto &m : f->marks) f->spare.push_back(m);
+        f->marks.clear();
+    }
+    return WFST_OK;
+}
 
 int wfst_fst_health(const wfst_fst *f, uint32_t *flags, int32_t clear, void *stream)
 {
@@ -725,8 +815,10 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     if (grad_final) return set_err(WFST_EUNSUPPORTED, "grad_final is not supported by this build");
     wfst_fst *f = const_cast<wfst_fst *>(fc);
     hipStream_t s = as_stream(stream);
-    if (f->A > 0)
+    if (f->A > 0) {
+        ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
         hipLaunchKernelGGL(fill_f32, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s, grad_arc_score, f->A, 0.0f);
+    }
     const int32_t B = tape->B;
     const int64_t N = tape->N;
     if (B == 0 || N == 0) {
