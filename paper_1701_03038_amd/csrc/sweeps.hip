@@ -594,15 +594,94 @@ struct CountItem {
     int32_t split;        // 1 when the label's visits span several items
 };
 
+// Everything the count kernel needs about one visit (sentence b, step t,
+// token i), in one record: posterior of arc k at this visit is
+//   g * exp((alpha~_{t-1}[src_k] - cm) + score_k + (beta~_t[dst_k] - bm) + o).
+struct VisitInfo {
+    int64_t a_off;       // compact alpha of step t-1 (token i-1)
+    int64_t b_off;       // compact beta of step t (token i)
+    int32_t prev_label;  // label of token i-1, -1 at t = 1 (alpha_0 = start)
+    int32_t live;        // 0: sentence without a path (or invalid): skip
+    float o, cm, bm, g;
+};
+
+// One thread per visit position of the label-sorted list.
+__global__ void visit_table(BatchView bv, TapeView tp, const int32_t *__restrict__ visits,
+                            const int32_t *__restrict__ tok_sent, const float *__restrict__ grad_log_z,
+                            VisitInfo *__restrict__ out)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < bv.N; v += (int64_t)gridDim.x * blockDim.x) {
+        VisitInfo vi{};
+        vi.prev_label = -1;
+        const int i = visits[v];
+        bool ok = i >= 0 && (int64_t)i < bv.N;
+        const int b = ok ? tok_sent[i] : 0;
+        ok = ok && b >= 0 && b < bv.B;
+        int o0 = 0;
+        if (ok) {
+            o0 = bv.offsets[b];
+            ok = i >= o0 && i < bv.offsets[b + 1];
+        }
+        if (!ok) atomicOr(bv.health, H_VISIT);
+        if (ok && bv.status[b] == WFST_STATUS_OK) {
+            const int t = i - o0 + 1;
+            const double aC = t > 1 ? tp.a_log[i - 1] : 0.0;
+            vi.o = (float)(aC + tp.b_log[i] - tp.log_z[b]);
+            vi.cm = t > 1 ? tp.a_max[i - 1] : 0.0f;
+            vi.bm = tp.b_max[i];
+            vi.g = grad_log_z ? grad_log_z[b] : 1.0f;
+            vi.a_off = t > 1 ? bv.tok_off[i - 1] : 0;
+            vi.b_off = bv.tok_off[i];
+            vi.prev_label = t > 1 ? bv.tokens[i - 1] : -1;
+            vi.live = 1;
+        }
+        out[v] = vi;
+    }
+}
+
+// Expected counts (paper, Algorithm 2 last loop), grouped by input label so
+// that each arc's sum over the visits of its label is taken in a fixed order,
+// without atomics.  A work item is one label and up to V of its visits; the
+// label's arc slices are streamed once per visit, the previous step's alpha is
+// scattered into a stamped dense LDS vector, and the next visit's record and
+// alpha values are loaded while the current visit computes.
 // CH is the layout's chunk size (slice heights never exceed it); each lane
 // keeps KPP * CH = 64 accumulators in registers, so one pass covers KPP
 // slices per wavefront and wide labels take several passes over their visits.
+constexpr int kPrefetch = 4;  // alpha entries per thread carried to the next visit
+
+template <int NT>
+__device__ __forceinline__ void fetch_alpha(const DevLayout &fl, const TapeView &tp, const VisitInfo &vi,
+                                            int32_t start, int tid, int (&key)[kPrefetch],
+                                            float (&val)[kPrefetch])
+{
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) key[u] = -1;
+    if (!vi.live) return;
+    if (vi.prev_label < 0) {
+        if (tid == 0) {
+            key[0] = start;
+            val[0] = 0.0f;
+        }
+        return;
+    }
+    const LabelInfo lp = fl.label[vi.prev_label];
+    const float *ta = tp.alpha + vi.a_off;
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int j = tid + u * NT;
+        if (j < lp.n_segs) {
+            key[u] = fl.seg_key[lp.seg_first + j];
+            val[u] = ta[j] - vi.cm;
+        }
+    }
+}
+
 template <int NT, int CH>
 __global__ void __launch_bounds__(NT)
 counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
               const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
-              const int32_t *__restrict__ visits, const int32_t *__restrict__ tok_sent,
-              const float *__restrict__ grad_log_z, float *__restrict__ grad,
+              const VisitInfo *__restrict__ vinfo, float *__restrict__ grad,
               float *__restrict__ partial, int32_t *__restrict__ item_slot,
               int32_t *__restrict__ slot_counter, CountCaps caps)
 {
@@ -656,39 +735,28 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
             float acc[MAXR];
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) acc[r] = 0.0f;
+            VisitInfo vi = vinfo[ci.first];
+            int key[kPrefetch];
+            float val[kPrefetch];
+            fetch_alpha<NT>(fl, tp, vi, start, tid, key, val);
             for (int v = ci.first; v < ci.last; ++v) {
-                const int i = visits[v];
-                bool live = i >= 0 && (int64_t)i < bv.N;
-                const int b = live ? tok_sent[i] : 0;
-                live = live && b >= 0 && b < bv.B;
-                if (live) {
-                    const int o0 = bv.offsets[b], o1 = bv.offsets[b + 1];
-                    live = i >= o0 && i < o1 && bv.tokens[i] == ci.label;
-                }
-                if (!live && tid == 0) atomicOr(bv.health, H_VISIT);
-                live = live && bv.status[b] == WFST_STATUS_OK;
                 CEnt *den = (v & 1) ? den1 : den0;
-                float o = 0.0f, g = 1.0f;
-                int t = 0;
-                if (live) {
-                    t = i - bv.offsets[b] + 1;
-                    const double aC = t > 1 ? tp.a_log[i - 1] : 0.0;
-                    o = (float)(aC + tp.b_log[i] - tp.log_z[b]);
-                    g = grad_log_z ? grad_log_z[b] : 1.0f;
-                    if (t == 1) {
-                        if (tid == 0) den[start] = CEnt{0.0f, v};
-                    } else {
-                        const LabelInfo lp = fl.label[bv.tokens[i - 1]];
-                        const float *ta = tp.alpha + bv.tok_off[i - 1];
-                        const float cm = tp.a_max[i - 1];
-                        for (int j = tid; j < lp.n_segs; j += NT)
-                            den[fl.seg_key[lp.seg_first + j]] = CEnt{ta[j] - cm, v};
-                    }
+#pragma unroll
+                for (int u = 0; u < kPrefetch; ++u)
+                    if (key[u] >= 0) den[key[u]] = CEnt{val[u], v};
+                if (vi.live && vi.prev_label >= 0) {  // rare: more alpha entries than NT * kPrefetch
+                    const LabelInfo lp = fl.label[vi.prev_label];
+                    for (int j = tid + kPrefetch * NT; j < lp.n_segs; j += NT)
+                        den[fl.seg_key[lp.seg_first + j]] = CEnt{tp.alpha[vi.a_off + j] - vi.cm, v};
+                }
+                const VisitInfo cur = vi;
+                if (v + 1 < ci.last) {  // next visit's record and alpha, in flight during this one
+                    vi = vinfo[v + 1];
+                    fetch_alpha<NT>(fl, tp, vi, start, tid, key, val);
                 }
                 __syncthreads();
-                if (!live) continue;
-                const float *tb = tp.beta + bv.tok_off[i];
-                const float bm = tp.b_max[i];
+                if (!cur.live) continue;
+                const float *tb = tp.beta + cur.b_off;
 #pragma unroll
                 for (int k = 0; k < KPP; ++k) {
                     const int s = (pass * KPP + k) * NW + wave;
@@ -697,15 +765,15 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
                         if (lane < si.width) {
                             const int c = s * 64 + lane;
                             const int j = c < li.n_slots ? chunk_seg[c] : li.n_multi + (c - li.n_slots);
-                            const float bh = tb[j] - bm;
+                            const float bh = (tb[j] - cur.bm) + cur.o;
                             const Elem *ep = fl.elem + si.base + lane;
 #pragma unroll
                             for (int r = 0; r < CH; ++r) {
                                 if (r < si.height) {
                                     const Elem e = ep[r * si.width];
                                     const CEnt ae = den[e.other];
-                                    const float x = ((ae.v + e.score) + bh) + o;
-                                    const float add = g * exp_e(x);
+                                    const float x = (ae.v + e.score) + bh;
+                                    const float add = cur.g * exp_e(x);
                                     acc[k * CH + r] += ae.stamp == v ? add : 0.0f;
                                 }
                             }
@@ -724,12 +792,12 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
                         for (int r = 0; r < CH; ++r) {
                             if (r < si.height) {
                                 const int pos = si.base + r * si.width + lane;
-                                const float val = acc[k * CH + r];
+                                const float val2 = acc[k * CH + r];
                                 if (slot == -1) {
                                     const int arc = fl.elem_arc[pos];
-                                    if (arc >= 0) grad[arc] = val;
+                                    if (arc >= 0) grad[arc] = val2;
                                 } else if (slot >= 0) {
-                                    partial[(int64_t)slot * fl.max_elems + (pos - li.elem_first)] = val;
+                                    partial[(int64_t)slot * fl.max_elems + (pos - li.elem_first)] = val2;
                                 }
                             }
                         }
@@ -740,35 +808,68 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
     }
 }
 
-// Sums the partial counts of labels whose visits span several items, in item order.
+// Sums the partial counts of labels whose visits span several work items.
+// One thread per (split label, element): se_off[a] is the exclusive prefix of
+// the element counts of split labels, so thread w finds its label by binary
+// search; the label's items are consecutive and are summed in item order.
 template <int NT>
 __global__ void __launch_bounds__(NT)
-counts_fixup(DevLayout fl, const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
+counts_fixup(DevLayout fl, const int32_t *__restrict__ item_base, const int32_t *__restrict__ n_items_label,
+             const int64_t *__restrict__ se_off, const int64_t *__restrict__ se_total,
              const int32_t *__restrict__ item_slot, const float *__restrict__ partial,
              float *__restrict__ grad, CountCaps caps, int32_t M, uint32_t *health)
 {
-    int nit = *n_items;
-    if (nit < 0 || nit > caps.items_cap) nit = 0;  // the count kernel already flagged it
-    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
-        const CountItem ci = items[it];
-        if (!ci.split || ci.label < 0 || ci.label >= M) continue;
-        if (it > 0 && items[it - 1].label == ci.label) continue;  // first item of the label only
-        int last = it;
-        while (last + 1 < nit && items[last + 1].label == ci.label) ++last;
-        const LabelInfo li = fl.label[ci.label];
-        bool ok = true;
-        for (int k = it; k <= last; ++k) ok = ok && item_slot[k] >= 0 && item_slot[k] < caps.slot_cap;
-        if (!ok) {
-            if (threadIdx.x == 0) atomicOr(health, H_SLOT);
+    const int64_t W = *se_total;
+    for (int64_t w = blockIdx.x * (int64_t)NT + threadIdx.x; w < W; w += (int64_t)gridDim.x * NT) {
+        int lo = 0, hi = M;  // last label with se_off <= w
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (se_off[mid] <= w) lo = mid; else hi = mid;
+        }
+        const int a = lo;
+        const LabelInfo li = fl.label[a];
+        const int64_t e = w - se_off[a];
+        const int first = item_base[a], k = n_items_label[a];
+        if (e >= li.n_elems || k < 2 || first < 0 || first + k > caps.items_cap) {
+            atomicOr(health, H_ITEM);
             continue;
         }
-        for (int e = threadIdx.x; e < li.n_elems; e += NT) {
-            float s = 0.0f;
-            for (int k = it; k <= last; ++k) s += partial[(int64_t)item_slot[k] * fl.max_elems + e];
-            const int arc = fl.elem_arc[li.elem_first + e];
-            if (arc >= 0) grad[arc] = s;
+        float s = 0.0f;
+        bool ok = true;
+        int x = 0;
+        for (; x + 4 <= k; x += 4) {
+            int sl[4];
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sl[u] = item_slot[first + x + u];
+                ok = ok && sl[u] >= 0 && sl[u] < caps.slot_cap;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = ok ? partial[(int64_t)sl[u] * fl.max_elems + e] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += v[u];
         }
+        for (; x < k; ++x) {
+            const int sl = item_slot[first + x];
+            ok = ok && sl >= 0 && sl < caps.slot_cap;
+            if (ok) s += partial[(int64_t)sl * fl.max_elems + e];
+        }
+        if (!ok) {
+            atomicOr(health, H_SLOT);
+            continue;
+        }
+        const int arc = fl.elem_arc[li.elem_first + e];
+        if (arc >= 0) grad[arc] = s;
     }
+}
+
+// element count of every label whose visits span several count work items
+__global__ void split_label_elems(const LabelInfo *__restrict__ label, const int32_t *__restrict__ n_items_label,
+                                  int32_t M, int32_t *__restrict__ out)
+{
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < M; a += gridDim.x * blockDim.x)
+        out[a] = n_items_label[a] > 1 ? label[a].n_elems : 0;
 }
 
 // =====================================================================

@@ -90,11 +90,12 @@ int ensure_t(Buf &b, int64_t count, hipStream_t s, T **out)
 enum WsSlot {
     W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
-    W_PARTIAL, W_NUM
+    W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_NUM
 };
 
 // small device counters kept together (one allocation)
-enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_TOTAL = 4 /* int64 at byte 16 */, C_COUNT = 8 };
+enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_TOTAL = 4 /* int64 at byte 16 */,
+               C_SETOTAL = 6 /* int64 at byte 24 */, C_COUNT = 8 };
 
 struct TapeBufs {
     Buf order, tok_off, alpha, a_max, a_log, log_z, tiles, total;
@@ -361,9 +362,8 @@ int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const
 
 template <int CH>
 int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
-                     const CountItem *items, const int32_t *n_items, int64_t items_bound, const int32_t *visits,
-                     const int32_t *tok_sent, const float *g, float *grad, float *partial, int32_t *item_slot,
-                     int32_t *slot_counter, CountCaps caps)
+                     const CountItem *items, const int32_t *n_items, int64_t items_bound, const VisitInfo *vinfo,
+                     float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter, CountCaps caps)
 {
     constexpr int NT = 256;
     const size_t lds = lds_counts(f);
@@ -371,7 +371,7 @@ int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, cons
     TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
     ProfScope prof(f, s, WFST_KERNEL_COUNTS);
     hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start, bv, tp,
-                       items, n_items, visits, tok_sent, g, grad, partial, item_slot, slot_counter, caps);
+                       items, n_items, vinfo, grad, partial, item_slot, slot_counter, caps);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -874,26 +874,43 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     caps.items_cap = (int32_t)items_bound;
     caps.slot_cap = (int32_t)split_bound;
     caps.V = V;
+    VisitInfo *vinfo;
+    TRY(ensure_t(f->ws[W_VINFO], N, s, &vinfo));
+    hipLaunchKernelGGL(visit_table, dim3(grid_for(N, 256)), dim3(256), 0, s, bv, tp, (const int32_t *)visits,
+                       (const int32_t *)tok_sent, grad_log_z, vinfo);
     const int ch = f->chunk;
     if (ch <= 4)
-        rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent, grad_log_z,
-                                 grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
+        rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+                                 partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 8)
-        rc = launch_counts_ch<8>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent, grad_log_z,
-                                 grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
+        rc = launch_counts_ch<8>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+                                 partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 16)
-        rc = launch_counts_ch<16>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
-                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
+        rc = launch_counts_ch<16>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+                                  partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 32)
-        rc = launch_counts_ch<32>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
-                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
+        rc = launch_counts_ch<32>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+                                  partial, item_slot, counters + C_SLOTS, caps);
     else
-        rc = launch_counts_ch<64>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, visits, tok_sent,
-                                  grad_log_z, grad_arc_score, partial, item_slot, counters + C_SLOTS, caps);
+        rc = launch_counts_ch<64>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+                                  partial, item_slot, counters + C_SLOTS, caps);
     if (rc != WFST_OK) return rc;
-    hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(items_bound, 1, 4096)), dim3(256), 0, s, f->fwd,
-                       (const CountItem *)items, (const int32_t *)(counters + C_NITEMS), (const int32_t *)item_slot,
-                       (const float *)partial, grad_arc_score, caps, f->M, f->health);
+    // labels split over several items: one thread per (label, element) sums the partials
+    int32_t *split_e;
+    int64_t *se_off;
+    TRY(ensure_t(f->ws[W_SPLITE], f->M, s, &split_e));
+    TRY(ensure_t(f->ws[W_SEOFF], f->M, s, &se_off));
+    hipLaunchKernelGGL(split_label_elems, dim3(grid_for(f->M, 256)), dim3(256), 0, s,
+                       (const LabelInfo *)f->fwd.label, (const int32_t *)nip, f->M, split_e);
+    ScanSource ssrc;
+    ssrc.i32 = split_e;
+    int64_t *se_total = reinterpret_cast<int64_t *>(counters + C_SETOTAL);
+    TRY(launch_scan<int64_t>(s, ssrc, f->M, tiles, se_off, se_total));
+    const int64_t fix_bound = std::min<int64_t>(split_bound, f->M) * (int64_t)std::max(f->fwd.max_elems, 1);
+    hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(fix_bound, 256, 16384)), dim3(256), 0, s, f->fwd,
+                       (const int32_t *)item_base, (const int32_t *)nip, (const int64_t *)se_off,
+                       (const int64_t *)se_total, (const int32_t *)item_slot, (const float *)partial,
+                       grad_arc_score, caps, f->M, f->health);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
