@@ -83,8 +83,10 @@ typedef struct wfst_fst_info {
 } wfst_fst_info;
 
 /*
- * Build the device layouts of an FST (paper, section 4 CSR/COO per symbol,
- * reorganised per destination: see the layout notes in DESIGN).
+ * Build the device layouts of an FST (paper, section 4: arcs grouped per
+ * input symbol; here further grouped by destination state for the forward and
+ * Viterbi passes and by source state for the backward pass, and sliced for
+ * 64-wide wavefronts).
  *   src, dst, ilabel: host int32[num_arcs], ranges [0,num_states) / [0,num_ilabels).
  *   olabel: host int32[num_arcs] or NULL (then best_olabels can not be asked for).
  *   arc_score: host float[num_arcs], finite (NaN/inf -> WFST_EINVAL); -0 is
