@@ -98,6 +98,19 @@ __device__ __forceinline__ Lse wave_lse(Lse v)
     return v;
 }
 
+// Rows of a lane's chunk loaded together before they are reduced: enough
+// independent 8-byte loads in flight per wavefront to cover HBM latency.
+// Rows past the slice height read the dead state (index Q, value -inf).
+constexpr int kRowBatch = 16;
+
+__device__ __forceinline__ void load_rows(const Elem *ep, int width, int height, int r0, int32_t dead,
+                                          Elem (&e)[kRowBatch])
+{
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u)
+        e[u] = r0 + u < height ? ep[(r0 + u) * width] : Elem{dead, 0.0f};
+}
+
 // Validates the sentence's offsets and tokens; returns a WFST_STATUS_* code.
 template <int NT>
 __device__ int check_sentence(const BatchView &bv, int b, int &o0, int &o1)
@@ -193,13 +206,17 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                     const Elem *ep = fl.elem + si.base + lane;
                     float best = WFST_NINF;
                     int bpos = -1, bsrc = 0;
-                    for (int r = 0; r < si.height; ++r) {
-                        const Elem e = ep[r * si.width];
-                        const float v = prev[e.other].v + e.score;
-                        if (v > best) {
-                            best = v;
-                            bpos = si.base + r * si.width + lane;
-                            bsrc = e.other;
+                    for (int r0 = 0; r0 < si.height; r0 += kRowBatch) {
+                        Elem e[kRowBatch];
+                        load_rows(ep, si.width, si.height, r0, Q, e);
+#pragma unroll
+                        for (int u = 0; u < kRowBatch; ++u) {
+                            const float v = prev[e[u].other].v + e[u].score;
+                            if (v > best) {
+                                best = v;
+                                bpos = si.base + (r0 + u) * si.width + lane;
+                                bsrc = e[u].other;
+                            }
                         }
                     }
                     const int pred = bpos >= 0 ? prev[bsrc].idx : -1;
@@ -311,7 +328,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 template <int NT>
 __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &li, const float *prev,
                                           float *cur, float c_prev, Lse *part, float *tape, int lane,
-                                          int wave)
+                                          int wave, int32_t dead)
 {
     constexpr int NW = NT / 64;
     float my_max = WFST_NINF;
@@ -320,10 +337,14 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
         if (lane < si.width) {
             const Elem *ep = L.elem + si.base + lane;
             Lse acc{WFST_NINF, 0.0f};
-            for (int r = 0; r < si.height; ++r) {
-                const Elem e = ep[r * si.width];
-                const float g = prev[e.other];
-                if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e.score);
+            for (int r0 = 0; r0 < si.height; r0 += kRowBatch) {
+                Elem e[kRowBatch];
+                load_rows(ep, si.width, si.height, r0, dead, e);
+#pragma unroll
+                for (int u = 0; u < kRowBatch; ++u) {
+                    const float g = prev[e[u].other];
+                    if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e[u].score);
+                }
             }
             const int c = s * 64 + lane;
             if (c < li.n_slots) {
@@ -426,7 +447,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             const int i = o0 + t - 1;
             const LabelInfo li = fl.label[bv.tokens[i]];
             float *tape = tp.alpha + bv.tok_off[i];
-            const float mx = lse_step<NT>(fl, li, prev, cur, c_prev, part, tape, lane, wave);
+            const float mx = lse_step<NT>(fl, li, prev, cur, c_prev, part, tape, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
@@ -546,7 +567,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
             const int i = o0 + t - 1;
             const LabelInfo li = rl.label[bv.tokens[i]];
-            const float mx = lse_step<NT>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave);
+            const float mx = lse_step<NT>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave, Q);
             if (t == T) {
                 for (int q = tid; q < Q; q += NT) prev[q] = WFST_NINF;
             } else {
