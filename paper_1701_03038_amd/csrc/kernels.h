@@ -17,7 +17,7 @@ struct DevLayout {
     SegChunk *seg_chunk = nullptr;
     LabelInfo *label = nullptr;
     int64_t n_elem = 0, n_slice = 0, n_seg = 0;
-    int32_t max_segs = 0, max_slots = 0, max_elems = 0, max_height = 0;
+    int32_t max_segs = 0, max_slots = 0, max_elems = 0, max_height = 0, max_slices = 0;
 };
 
 // What every batched sweep needs about the batch.

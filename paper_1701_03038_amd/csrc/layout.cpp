@@ -175,6 +175,7 @@ int build_layout(int32_t Q, int32_t M, int64_t A, const int32_t *src, const int3
         out.max_slots = std::max(out.max_slots, c.n_slots);
         out.max_elems = (int32_t)std::min<int64_t>(INT32_MAX, std::max<int64_t>(out.max_elems, c.elems));
         out.max_height = std::max(out.max_height, c.max_h);
+        out.max_slices = std::max(out.max_slices, c.slices);
     }
     if (e_run >= INT32_MAX || s_run >= INT32_MAX || g_run >= INT32_MAX) {
         err = "layout exceeds 2^31-1 elements, slices or segments";

@@ -59,7 +59,7 @@ struct HostLayout {
     std::vector<int32_t> seg_key;    // key state per segment
     std::vector<SegChunk> seg_chunk;
     std::vector<LabelInfo> label;    // num_ilabels entries
-    int32_t max_segs = 0, max_slots = 0, max_elems = 0, max_height = 0;
+    int32_t max_segs = 0, max_slots = 0, max_elems = 0, max_height = 0, max_slices = 0;
 };
 
 // direction 0: key = dst, other = src (forward); 1: key = src, other = dst.

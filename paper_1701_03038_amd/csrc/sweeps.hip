@@ -568,10 +568,10 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             const int i = o0 + t - 1;
             const LabelInfo li = rl.label[bv.tokens[i]];
             const float mx = lse_step<NT>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave, Q);
-            if (t == T) {
+            const LabelInfo lp = rl.label[bv.tokens[t == T ? i : i + 1]];
+            if (t == T || 4 * lp.n_segs >= Q) {  // wide support: clear the whole vector, no key loads
                 for (int q = tid; q < Q; q += NT) prev[q] = WFST_NINF;
             } else {
-                const LabelInfo lp = rl.label[bv.tokens[i + 1]];
                 for (int j = tid; j < lp.n_segs; j += NT) prev[rl.seg_key[lp.seg_first + j]] = WFST_NINF;
             }
             if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
@@ -662,13 +662,18 @@ __global__ void visit_table(BatchView bv, TapeView tp, const int32_t *__restrict
 
 // Expected counts (paper, Algorithm 2 last loop), grouped by input label so
 // that each arc's sum over the visits of its label is taken in a fixed order,
-// without atomics.  A work item is one label and up to V of its visits; the
-// label's arc slices are streamed once per visit, the previous step's alpha is
-// scattered into a stamped dense LDS vector, and the next visit's record and
-// alpha values are loaded while the current visit computes.
-// CH is the layout's chunk size (slice heights never exceed it); each lane
-// keeps KPP * CH = 64 accumulators in registers, so one pass covers KPP
-// slices per wavefront and wide labels take several passes over their visits.
+// without atomics.  A work item is one label and up to V of its visits.  The
+// label's arcs are walked in the reverse layout: every lane chunk belongs to
+// one source state, so one lookup of alpha_{t-1} at that source decides
+// whether any of the chunk's arcs has a nonzero posterior at this visit; a
+// slice whose 64 sources are all dead is skipped after one ballot.  Arcs
+// skipped this way would add exactly +0, so the sums equal the dense ones.
+// alpha_{t-1} is scattered into a stamped dense LDS vector per visit; beta_t
+// is read from the tape through a per-label map state -> forward segment.
+// CH bounds the slice height; each lane keeps KPP * CH <= 64 accumulators in
+// registers, so one pass covers KPP slices per wavefront and labels with more
+// slices take several passes over their visits.
+constexpr int count_slices_per_wave(int ch) { return 64 / ch < 8 ? 64 / ch : 8; }
 constexpr int kPrefetch = 4;  // alpha entries per thread carried to the next visit
 
 template <int NT>
@@ -700,19 +705,20 @@ __device__ __forceinline__ void fetch_alpha(const DevLayout &fl, const TapeView 
 
 template <int NT, int CH>
 __global__ void __launch_bounds__(NT)
-counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
+counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
               const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
               const VisitInfo *__restrict__ vinfo, float *__restrict__ grad,
               float *__restrict__ partial, int32_t *__restrict__ item_slot,
               int32_t *__restrict__ slot_counter, CountCaps caps)
 {
     constexpr int NW = NT / 64;
-    constexpr int KPP = 64 / CH;
+    constexpr int KPP = count_slices_per_wave(CH);
     constexpr int MAXR = KPP * CH;
     extern __shared__ __align__(16) unsigned char smem[];
     CEnt *den0 = reinterpret_cast<CEnt *>(smem);
     CEnt *den1 = den0 + (Q + 1);
-    int32_t *chunk_seg = reinterpret_cast<int32_t *>(den1 + (Q + 1));
+    int32_t *fmap = reinterpret_cast<int32_t *>(den1 + (Q + 1));  // [Q] state -> forward segment of the label
+    int32_t *chunk_seg = fmap + Q;                                 // reverse chunk -> segment (multi-chunk)
     __shared__ int s_slot;
 
     const int tid = threadIdx.x;
@@ -734,10 +740,12 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
             if (tid == 0) atomicOr(bv.health, H_ITEM);
             continue;
         }
-        const LabelInfo li = fl.label[ci.label];
+        const LabelInfo li = rl.label[ci.label];
+        const LabelInfo lf = fl.label[ci.label];
         __syncthreads();
+        for (int j = tid; j < lf.n_segs; j += NT) fmap[fl.seg_key[lf.seg_first + j]] = j;
         for (int j = tid; j < li.n_multi; j += NT) {
-            const SegChunk sc = fl.seg_chunk[li.seg_first + j];
+            const SegChunk sc = rl.seg_chunk[li.seg_first + j];
             for (int p = 0; p < sc.count; ++p) chunk_seg[sc.first + p] = j;
         }
         if (ci.split && tid == 0) {
@@ -756,6 +764,20 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
             float acc[MAXR];
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) acc[r] = 0.0f;
+            int src[KPP];  // source state of this lane's chunk in each slice of the pass (-1: none)
+#pragma unroll
+            for (int k = 0; k < KPP; ++k) {
+                const int s = (pass * KPP + k) * NW + wave;
+                src[k] = -1;
+                if (s < li.n_slices) {
+                    const SliceInfo si = rl.slice[li.slice_first + s];
+                    if (lane < si.width) {
+                        const int c = s * 64 + lane;
+                        const int j = c < li.n_slots ? chunk_seg[c] : li.n_multi + (c - li.n_slots);
+                        src[k] = rl.seg_key[li.seg_first + j];
+                    }
+                }
+            }
             VisitInfo vi = vinfo[ci.first];
             int key[kPrefetch];
             float val[kPrefetch];
@@ -780,22 +802,24 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
                 const float *tb = tp.beta + cur.b_off;
 #pragma unroll
                 for (int k = 0; k < KPP; ++k) {
-                    const int s = (pass * KPP + k) * NW + wave;
-                    if (s < li.n_slices) {
-                        const SliceInfo si = fl.slice[li.slice_first + s];
-                        if (lane < si.width) {
-                            const int c = s * 64 + lane;
-                            const int j = c < li.n_slots ? chunk_seg[c] : li.n_multi + (c - li.n_slots);
-                            const float bh = (tb[j] - cur.bm) + cur.o;
-                            const Elem *ep = fl.elem + si.base + lane;
+                    float a = WFST_NINF;
+                    if (src[k] >= 0) {
+                        const CEnt ae = den[src[k]];
+                        if (ae.stamp == v) a = ae.v;
+                    }
+                    const bool live = a != WFST_NINF;
+                    if (__ballot(live) != 0ull && live) {
+                        const int s = (pass * KPP + k) * NW + wave;
+                        const SliceInfo si = rl.slice[li.slice_first + s];
+                        const Elem *ep = rl.elem + si.base + lane;
 #pragma unroll
-                            for (int r = 0; r < CH; ++r) {
-                                if (r < si.height) {
-                                    const Elem e = ep[r * si.width];
-                                    const CEnt ae = den[e.other];
-                                    const float x = (ae.v + e.score) + bh;
-                                    const float add = cur.g * exp_e(x);
-                                    acc[k * CH + r] += ae.stamp == v ? add : 0.0f;
+                        for (int r = 0; r < CH; ++r) {
+                            if (r < si.height) {
+                                const Elem e = ep[r * si.width];
+                                if (e.other < Q) {
+                                    const float bh = (tb[fmap[e.other]] - cur.bm) + cur.o;
+                                    const float x = (a + e.score) + bh;
+                                    acc[k * CH + r] += cur.g * exp_e(x);
                                 }
                             }
                         }
@@ -807,7 +831,7 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
             for (int k = 0; k < KPP; ++k) {
                 const int s = (pass * KPP + k) * NW + wave;
                 if (s < li.n_slices) {
-                    const SliceInfo si = fl.slice[li.slice_first + s];
+                    const SliceInfo si = rl.slice[li.slice_first + s];
                     if (lane < si.width) {
 #pragma unroll
                         for (int r = 0; r < CH; ++r) {
@@ -815,10 +839,10 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
                                 const int pos = si.base + r * si.width + lane;
                                 const float val2 = acc[k * CH + r];
                                 if (slot == -1) {
-                                    const int arc = fl.elem_arc[pos];
+                                    const int arc = rl.elem_arc[pos];
                                     if (arc >= 0) grad[arc] = val2;
                                 } else if (slot >= 0) {
-                                    partial[(int64_t)slot * fl.max_elems + (pos - li.elem_first)] = val2;
+                                    partial[(int64_t)slot * rl.max_elems + (pos - li.elem_first)] = val2;
                                 }
                             }
                         }
@@ -829,10 +853,6 @@ counts_kernel(DevLayout fl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
     }
 }
 
-// Sums the partial counts of labels whose visits span several work items.
-// One thread per (split label, element): se_off[a] is the exclusive prefix of
-// the element counts of split labels, so thread w finds its label by binary
-// search; the label's items are consecutive and are summed in item order.
 template <int NT>
 __global__ void __launch_bounds__(NT)
 counts_fixup(DevLayout fl, const int32_t *__restrict__ item_base, const int32_t *__restrict__ n_items_label,

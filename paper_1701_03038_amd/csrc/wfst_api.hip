@@ -171,6 +171,7 @@ int upload_layout(wfst_fst *f, const HostLayout &h, DevLayout &d, hipStream_t s)
     d.max_slots = h.max_slots;
     d.max_elems = h.max_elems;
     d.max_height = h.max_height;
+    d.max_slices = h.max_slices;
     return WFST_OK;
 }
 
@@ -237,7 +238,8 @@ size_t lds_lse(const wfst_fst *f, const DevLayout &l)
 }
 size_t lds_counts(const wfst_fst *f)
 {
-    return (size_t)(f->Q + 1) * 2 * sizeof(CEnt) + (size_t)std::max(f->fwd.max_slots, 1) * sizeof(int32_t);
+    return (size_t)(f->Q + 1) * 2 * sizeof(CEnt) + (size_t)f->Q * sizeof(int32_t) +
+           (size_t)std::max(f->rev.max_slots, 1) * sizeof(int32_t);
 }
 
 template <class K>
@@ -360,20 +362,38 @@ int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const
     return WFST_OK;
 }
 
+template <int NT, int CH>
+int launch_counts_nt(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
+                     const CountItem *items, const int32_t *n_items, int64_t items_bound, const VisitInfo *vinfo,
+                     float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter, CountCaps caps)
+{
+    const size_t lds = lds_counts(f);
+    int grid = 0;
+    TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
+    ProfScope prof(f, s, WFST_KERNEL_COUNTS);
+    hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start, bv,
+                       tp, items, n_items, vinfo, grad, partial, item_slot, slot_counter, caps);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+// Workgroup size of the count kernel: enough wavefronts for the widest label
+// of the reverse layout to fit one pass (KPP = 64 / CH slices per wavefront).
 template <int CH>
 int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
                      const CountItem *items, const int32_t *n_items, int64_t items_bound, const VisitInfo *vinfo,
                      float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter, CountCaps caps)
 {
-    constexpr int NT = 256;
-    const size_t lds = lds_counts(f);
-    int grid = 0;
-    TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
-    ProfScope prof(f, s, WFST_KERNEL_COUNTS);
-    hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start, bv, tp,
-                       items, n_items, vinfo, grad, partial, item_slot, slot_counter, caps);
-    HIP_OK(hipGetLastError());
-    return WFST_OK;
+    constexpr int KPP = count_slices_per_wave(CH);
+    const int waves = (f->rev.max_slices + KPP - 1) / KPP;
+    if (waves > 8)
+        return launch_counts_nt<1024, CH>(f, s, bv, tp, items, n_items, items_bound, vinfo, grad, partial,
+                                          item_slot, slot_counter, caps);
+    if (waves > 4)
+        return launch_counts_nt<512, CH>(f, s, bv, tp, items, n_items, items_bound, vinfo, grad, partial,
+                                         item_slot, slot_counter, caps);
+    return launch_counts_nt<256, CH>(f, s, bv, tp, items, n_items, items_bound, vinfo, grad, partial, item_slot,
+                                     slot_counter, caps);
 }
 
 #define DISPATCH_NT(rc, nt, fn, ...)                  \
@@ -858,7 +878,7 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     TRY(ensure_t(f->ws[W_ITEMSLOT], items_bound, s, &item_slot));
     const int64_t split_bound = 2 * (N / V) + 2;
     float *partial;
-    TRY(ensure_t(f->ws[W_PARTIAL], split_bound * (int64_t)std::max(f->fwd.max_elems, 1), s, &partial));
+    TRY(ensure_t(f->ws[W_PARTIAL], split_bound * (int64_t)std::max(f->rev.max_elems, 1), s, &partial));
     int64_t *tiles;
     TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(std::max<int64_t>(f->M, 256 * ((N + kSortTile - 1) / kSortTile))),
                  s, &tiles));
@@ -878,7 +898,7 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     TRY(ensure_t(f->ws[W_VINFO], N, s, &vinfo));
     hipLaunchKernelGGL(visit_table, dim3(grid_for(N, 256)), dim3(256), 0, s, bv, tp, (const int32_t *)visits,
                        (const int32_t *)tok_sent, grad_log_z, vinfo);
-    const int ch = f->chunk;
+    const int ch = f->rev.max_height;  // slice height bound of the reverse layout
     if (ch <= 4)
         rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
                                  partial, item_slot, counters + C_SLOTS, caps);
@@ -901,13 +921,13 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     TRY(ensure_t(f->ws[W_SPLITE], f->M, s, &split_e));
     TRY(ensure_t(f->ws[W_SEOFF], f->M, s, &se_off));
     hipLaunchKernelGGL(split_label_elems, dim3(grid_for(f->M, 256)), dim3(256), 0, s,
-                       (const LabelInfo *)f->fwd.label, (const int32_t *)nip, f->M, split_e);
+                       (const LabelInfo *)f->rev.label, (const int32_t *)nip, f->M, split_e);
     ScanSource ssrc;
     ssrc.i32 = split_e;
     int64_t *se_total = reinterpret_cast<int64_t *>(counters + C_SETOTAL);
     TRY(launch_scan<int64_t>(s, ssrc, f->M, tiles, se_off, se_total));
-    const int64_t fix_bound = std::min<int64_t>(split_bound, f->M) * (int64_t)std::max(f->fwd.max_elems, 1);
-    hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(fix_bound, 256, 16384)), dim3(256), 0, s, f->fwd,
+    const int64_t fix_bound = std::min<int64_t>(split_bound, f->M) * (int64_t)std::max(f->rev.max_elems, 1);
+    hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(fix_bound, 256, 16384)), dim3(256), 0, s, f->rev,
                        (const int32_t *)item_base, (const int32_t *)nip, (const int64_t *)se_off,
                        (const int64_t *)se_total, (const int32_t *)item_slot, (const float *)partial,
                        grad_arc_score, caps, f->M, f->health);

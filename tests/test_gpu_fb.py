@@ -81,11 +81,13 @@ def test_single_sentences_posteriors_within_1e5(wf):
     assert abs(post.sum() - batch.tokens.size) < 1e-3
 
 
-@pytest.mark.parametrize("nt", [64, 256])
-def test_trigram_small(wf, nt):
-    say(f"case: trigram small fb nt={nt}")
+@pytest.mark.parametrize("nt,chunk", [(64, 0), (256, 0), (256, 4)])
+def test_trigram_small(wf, nt, chunk):
+    """45-tag trigram tagger, vocabulary 2000.  With 4-arc chunks the widest
+    label has ~65 reverse slices, which takes the 1024-thread count kernel."""
+    say(f"case: trigram small fb nt={nt} chunk={chunk}")
     fst, batch = synth.config(3, vocab=2000, batch=200)
-    d = wf.Fst.from_synth(fst, threads_per_sentence=nt)
+    d = wf.Fst.from_synth(fst, threads_per_sentence=nt, chunk_arcs=chunk)
     assert_fb_parity(fst, batch, d, "trigram small")
 
 
