@@ -10,7 +10,8 @@
 namespace wfst {
 
 struct DevLayout {
-    Elem *elem = nullptr;          // padded, slice-interleaved arc slots
+    int32_t *other = nullptr;      // padded, slice-interleaved arc slots: other end state
+    float *score = nullptr;        // ... and arc score
     int32_t *elem_arc = nullptr;   // arc id per slot (-1 padding)
     SliceInfo *slice = nullptr;
     int32_t *seg_key = nullptr;

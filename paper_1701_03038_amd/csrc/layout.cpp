@@ -181,7 +181,8 @@ int build_layout(int32_t Q, int32_t M, int64_t A, const int32_t *src, const int3
         err = "layout exceeds 2^31-1 elements, slices or segments";
         return WFST_EUNSUPPORTED;
     }
-    out.elem.resize((size_t)e_run);
+    out.other.resize((size_t)e_run);
+    out.score.resize((size_t)e_run);
     out.elem_arc.resize((size_t)e_run);
     out.slice.resize((size_t)s_run);
     out.seg_key.resize((size_t)g_run);
@@ -224,10 +225,12 @@ int build_layout(int32_t Q, int32_t M, int64_t A, const int32_t *src, const int3
                             const Seg &sg = segs[(size_t)cseg[(size_t)c]];
                             const int32_t arc = order[sg.start + (int64_t)cpart[(size_t)c] * L + r];
                             const float sc = score ? (score[arc] == 0.0f ? 0.0f : score[arc]) : 0.0f;
-                            out.elem[(size_t)e] = Elem{other[arc], sc};
+                            out.other[(size_t)e] = other[arc];
+                            out.score[(size_t)e] = sc;
                             out.elem_arc[(size_t)e] = arc;
                         } else {
-                            out.elem[(size_t)e] = Elem{Q, 0.0f};
+                            out.other[(size_t)e] = Q;
+                            out.score[(size_t)e] = 0.0f;
                             out.elem_arc[(size_t)e] = -1;
                         }
                     }

@@ -11,8 +11,10 @@
 // reduces one chunk serially.  Chunks of a label are packed 64 at a time into
 // *slices* (one wavefront): slice element (r, l) -- row r of the chunk held by
 // lane l -- lives at base + r * width + l, so a wavefront reading row r loads
-// `width` consecutive 8-byte elements.  Chunks shorter than the slice height
-// are padded with a dead element (key state = num_states, score 0).
+// `width` consecutive entries of each element array (other state, score).
+// Chunks shorter than the slice height are padded with a dead element (other
+// state = num_states, score 0).  Scores are an array of their own so that a
+// score update writes whole cache lines.
 //
 // Within a label, segments are ordered by decreasing arc count, then by key
 // state.  Segments with more than `chunk` arcs ("multi-chunk") therefore come
@@ -27,6 +29,7 @@
 
 namespace wfst {
 
+// One element as a kernel holds it in registers (stored as two arrays).
 struct Elem {
     int32_t other;  // the non-key end state of the arc (num_states = padding)
     float score;    // arc score (log domain)
@@ -53,7 +56,8 @@ struct SegChunk {
 
 struct HostLayout {
     int32_t num_states = 0, num_ilabels = 0, chunk = 0;
-    std::vector<Elem> elem;
+    std::vector<int32_t> other;      // non-key end state per element (num_states for padding)
+    std::vector<float> score;        // arc score per element (0 for padding)
     std::vector<int32_t> elem_arc;   // arc id per element, -1 for padding
     std::vector<SliceInfo> slice;
     std::vector<int32_t> seg_key;    // key state per segment

@@ -103,12 +103,12 @@ __device__ __forceinline__ Lse wave_lse(Lse v)
 // Rows past the slice height read the dead state (index Q, value -inf).
 constexpr int kRowBatch = 16;
 
-__device__ __forceinline__ void load_rows(const Elem *ep, int width, int height, int r0, int32_t dead,
-                                          Elem (&e)[kRowBatch])
+__device__ __forceinline__ void load_rows(const int32_t *op, const float *sp, int width, int height, int r0,
+                                          int32_t dead, Elem (&e)[kRowBatch])
 {
 #pragma unroll
     for (int u = 0; u < kRowBatch; ++u)
-        e[u] = r0 + u < height ? ep[(r0 + u) * width] : Elem{dead, 0.0f};
+        e[u] = r0 + u < height ? Elem{op[(r0 + u) * width], sp[(r0 + u) * width]} : Elem{dead, 0.0f};
 }
 
 // Validates the sentence's offsets and tokens; returns a WFST_STATUS_* code.
@@ -203,12 +203,13 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             for (int s = wave; s < li.n_slices; s += NW) {
                 const SliceInfo si = fl.slice[li.slice_first + s];
                 if (lane < si.width) {
-                    const Elem *ep = fl.elem + si.base + lane;
+                    const int32_t *op = fl.other + si.base + lane;
+                    const float *sp = fl.score + si.base + lane;
                     float best = WFST_NINF;
                     int bpos = -1, bsrc = 0;
                     for (int r0 = 0; r0 < si.height; r0 += kRowBatch) {
                         Elem e[kRowBatch];
-                        load_rows(ep, si.width, si.height, r0, Q, e);
+                        load_rows(op, sp, si.width, si.height, r0, Q, e);
 #pragma unroll
                         for (int u = 0; u < kRowBatch; ++u) {
                             const float v = prev[e[u].other].v + e[u].score;
@@ -325,37 +326,68 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 // previous vector (un-normalised; c_prev is subtracted on the fly), cur
 // receives LSE per segment key.  Returns this thread's max over what it wrote.
 // When tape != nullptr the value of segment j is also stored at tape[j].
-template <int NT>
+// A wavefront takes SB of its slices at a time and loads the first RB rows of
+// each before reducing any of them (more loads in flight when chunks are
+// short); a lane reduces its chunk's rows in row order.
+template <int NT, int SB, int RB>
 __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &li, const float *prev,
                                           float *cur, float c_prev, Lse *part, float *tape, int lane,
                                           int wave, int32_t dead)
 {
     constexpr int NW = NT / 64;
     float my_max = WFST_NINF;
-    for (int s = wave; s < li.n_slices; s += NW) {
-        const SliceInfo si = L.slice[li.slice_first + s];
-        if (lane < si.width) {
-            const Elem *ep = L.elem + si.base + lane;
-            Lse acc{WFST_NINF, 0.0f};
-            for (int r0 = 0; r0 < si.height; r0 += kRowBatch) {
-                Elem e[kRowBatch];
-                load_rows(ep, si.width, si.height, r0, dead, e);
+    for (int s0 = wave; s0 < li.n_slices; s0 += NW * SB) {
+        SliceInfo si[SB];
 #pragma unroll
-                for (int u = 0; u < kRowBatch; ++u) {
-                    const float g = prev[e[u].other];
-                    if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e[u].score);
+        for (int k = 0; k < SB; ++k) {
+            const int s = s0 + k * NW;
+            si[k] = s < li.n_slices ? L.slice[li.slice_first + s] : SliceInfo{0, 0, 0, 0};
+        }
+        Elem e[SB][RB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            const bool on = lane < si[k].width;
+            const int32_t *op = L.other + si[k].base + lane;
+            const float *sp = L.score + si[k].base + lane;
+#pragma unroll
+            for (int u = 0; u < RB; ++u)
+                e[k][u] = on && u < si[k].height ? Elem{op[u * si[k].width], sp[u * si[k].width]}
+                                                 : Elem{dead, 0.0f};
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            if (lane < si[k].width) {
+                Lse acc{WFST_NINF, 0.0f};
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    const float g = prev[e[k][u].other];
+                    if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e[k][u].score);
                 }
-            }
-            const int c = s * 64 + lane;
-            if (c < li.n_slots) {
-                part[c] = acc;
-            } else {
-                const int j = li.n_multi + (c - li.n_slots);
-                const int d = L.seg_key[li.seg_first + j];
-                const float v = lse_value(acc);
-                cur[d] = v;
-                if (tape) tape[j] = v;
-                my_max = fmaxf(my_max, v);
+                for (int r0 = RB; r0 < si[k].height; r0 += RB) {
+                    Elem f[RB];
+#pragma unroll
+                    for (int u = 0; u < RB; ++u)
+                        f[u] = r0 + u < si[k].height
+                                   ? Elem{L.other[si[k].base + (r0 + u) * si[k].width + lane],
+                                          L.score[si[k].base + (r0 + u) * si[k].width + lane]}
+                                   : Elem{dead, 0.0f};
+#pragma unroll
+                    for (int u = 0; u < RB; ++u) {
+                        const float g = prev[f[u].other];
+                        if (g != WFST_NINF) lse_push(acc, (g - c_prev) + f[u].score);
+                    }
+                }
+                const int c = (s0 + k * NW) * 64 + lane;
+                if (c < li.n_slots) {
+                    part[c] = acc;
+                } else {
+                    const int j = li.n_multi + (c - li.n_slots);
+                    const int d = L.seg_key[li.seg_first + j];
+                    const float v = lse_value(acc);
+                    cur[d] = v;
+                    if (tape) tape[j] = v;
+                    my_max = fmaxf(my_max, v);
+                }
             }
         }
     }
@@ -447,7 +479,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             const int i = o0 + t - 1;
             const LabelInfo li = fl.label[bv.tokens[i]];
             float *tape = tp.alpha + bv.tok_off[i];
-            const float mx = lse_step<NT>(fl, li, prev, cur, c_prev, part, tape, lane, wave, Q);
+            const float mx = lse_step<NT, 1, kRowBatch>(fl, li, prev, cur, c_prev, part, tape, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
@@ -567,7 +599,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
             const int i = o0 + t - 1;
             const LabelInfo li = rl.label[bv.tokens[i]];
-            const float mx = lse_step<NT>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave, Q);
+            const float mx = lse_step<NT, 4, 4>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave, Q);
             const LabelInfo lp = rl.label[bv.tokens[t == T ? i : i + 1]];
             if (t == T || 4 * lp.n_segs >= Q) {  // wide support: clear the whole vector, no key loads
                 for (int q = tid; q < Q; q += NT) prev[q] = WFST_NINF;
@@ -811,11 +843,12 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
                     if (__ballot(live) != 0ull && live) {
                         const int s = (pass * KPP + k) * NW + wave;
                         const SliceInfo si = rl.slice[li.slice_first + s];
-                        const Elem *ep = rl.elem + si.base + lane;
+                        const int32_t *op = rl.other + si.base + lane;
+                        const float *sp = rl.score + si.base + lane;
 #pragma unroll
                         for (int r = 0; r < CH; ++r) {
                             if (r < si.height) {
-                                const Elem e = ep[r * si.width];
+                                const Elem e{op[r * si.width], sp[r * si.width]};
                                 if (e.other < Q) {
                                     const float bh = (tb[fmap[e.other]] - cur.bm) + cur.o;
                                     const float x = (a + e.score) + bh;
@@ -1015,16 +1048,30 @@ __global__ void label_items(const int32_t *__restrict__ grp_lo, const int32_t *_
 }
 
 // new scores into a layout through its element -> arc map
-__global__ void scatter_scores(Elem *__restrict__ elem, const int32_t *__restrict__ elem_arc, int64_t n,
+// (four elements per thread; out and elem_arc are 16-byte aligned allocations)
+__device__ __forceinline__ float scatter_one(int arc, const float *__restrict__ score)
+{
+    if (arc < 0) return 0.0f;  // padding keeps score 0
+    const float s = score[arc];
+    return s == 0.0f ? 0.0f : s;
+}
+
+__global__ void scatter_scores(float *__restrict__ out, const int32_t *__restrict__ elem_arc, int64_t n,
                                const float *__restrict__ score)
 {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int arc = elem_arc[e];
-        if (arc >= 0) {
-            const float s = score[arc];
-            elem[e].score = s == 0.0f ? 0.0f : s;
-        }
+    const int64_t n4 = n / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n4; e += stride) {
+        const int4 a = reinterpret_cast<const int4 *>(elem_arc)[e];
+        float4 v;
+        v.x = scatter_one(a.x, score);
+        v.y = scatter_one(a.y, score);
+        v.z = scatter_one(a.z, score);
+        v.w = scatter_one(a.w, score);
+        reinterpret_cast<float4 *>(out)[e] = v;
     }
+    for (int64_t e = 4 * n4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += stride)
+        out[e] = scatter_one(elem_arc[e], score);
 }
 
 __global__ void final_max_kernel(const float *__restrict__ fin, int32_t Q, float *__restrict__ out)

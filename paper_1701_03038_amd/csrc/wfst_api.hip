@@ -158,13 +158,14 @@ int dev_upload(wfst_fst *f, T **dst, const T *src, int64_t count, hipStream_t s)
 
 int upload_layout(wfst_fst *f, const HostLayout &h, DevLayout &d, hipStream_t s)
 {
-    TRY(dev_upload(f, &d.elem, h.elem.data(), (int64_t)h.elem.size(), s));
+    TRY(dev_upload(f, &d.other, h.other.data(), (int64_t)h.other.size(), s));
+    TRY(dev_upload(f, &d.score, h.score.data(), (int64_t)h.score.size(), s));
     TRY(dev_upload(f, &d.elem_arc, h.elem_arc.data(), (int64_t)h.elem_arc.size(), s));
     TRY(dev_upload(f, &d.slice, h.slice.data(), (int64_t)h.slice.size(), s));
     TRY(dev_upload(f, &d.seg_key, h.seg_key.data(), (int64_t)h.seg_key.size(), s));
     TRY(dev_upload(f, &d.seg_chunk, h.seg_chunk.data(), (int64_t)h.seg_chunk.size(), s));
     TRY(dev_upload(f, &d.label, h.label.data(), (int64_t)h.label.size(), s));
-    d.n_elem = (int64_t)h.elem.size();
+    d.n_elem = (int64_t)h.other.size();
     d.n_slice = (int64_t)h.slice.size();
     d.n_seg = (int64_t)h.seg_key.size();
     d.max_segs = h.max_segs;
@@ -484,11 +485,11 @@ int wfst_layout_host(int32_t num_states, int32_t num_ilabels, int64_t num_arcs, 
         const int32_t L = chunk_arcs > 0 ? chunk_arcs : auto_chunk(num_states, num_ilabels, num_arcs);
         int rc = build_layout(num_states, num_ilabels, num_arcs, src, dst, ilabel, nullptr, direction, L, h, err);
         if (rc != WFST_OK) return set_err(rc, err);
-        sizes[0] = (int64_t)h.elem.size();
+        sizes[0] = (int64_t)h.other.size();
         sizes[1] = (int64_t)h.slice.size();
         sizes[2] = (int64_t)h.seg_key.size();
         if (elem_other)
-            for (size_t e = 0; e < h.elem.size(); ++e) elem_other[e] = h.elem[e].other;
+            std::memcpy(elem_other, h.other.data(), h.other.size() * sizeof(int32_t));
         if (elem_arc) std::memcpy(elem_arc, h.elem_arc.data(), h.elem_arc.size() * sizeof(int32_t));
         if (slice_info)
             for (size_t x = 0; x < h.slice.size(); ++x) {
@@ -631,9 +632,9 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
     hipStream_t s = as_stream(stream);
     if (arc_score_dev && f->A > 0) {
         ProfScope prof(f, s, WFST_KERNEL_SCORES);
-        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->fwd.n_elem, 256, 8192)), dim3(256), 0, s, f->fwd.elem,
+        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->fwd.n_elem / 4 + 1, 256, 8192)), dim3(256), 0, s, f->fwd.score,
                            (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, arc_score_dev);
-        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->rev.n_elem, 256, 8192)), dim3(256), 0, s, f->rev.elem,
+        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->rev.n_elem / 4 + 1, 256, 8192)), dim3(256), 0, s, f->rev.score,
                            (const int32_t *)f->rev.elem_arc, f->rev.n_elem, arc_score_dev);
     }
     if (final_score_dev) {
