@@ -694,32 +694,49 @@ __global__ void visit_table(BatchView bv, TapeView tp, const int32_t *__restrict
 
 // Expected counts (paper, Algorithm 2 last loop), grouped by input label so
 // that each arc's sum over the visits of its label is taken in a fixed order,
-// without atomics.  A work item is one label and up to V of its visits.  The
+// without atomics.  A work item is one label and up to V of its visits;
+// workgroups pop items from a queue (heaviest labels come first).  The
 // label's arcs are walked in the reverse layout: every lane chunk belongs to
 // one source state, so one lookup of alpha_{t-1} at that source decides
 // whether any of the chunk's arcs has a nonzero posterior at this visit; a
 // slice whose 64 sources are all dead is skipped after one ballot.  Arcs
 // skipped this way would add exactly +0, so the sums equal the dense ones.
-// alpha_{t-1} is scattered into a stamped dense LDS vector per visit; beta_t
-// is read from the tape through a per-label map state -> forward segment.
+// Per visit, alpha_{t-1} is scattered into a stamped dense LDS vector and
+// beta_t (with its normaliser and the visit's scale offset folded in) into an
+// LDS vector over the label's destinations; both are loaded one visit ahead.
 // CH bounds the slice height; each lane keeps KPP * CH <= 64 accumulators in
 // registers, so one pass covers KPP slices per wavefront and labels with more
 // slices take several passes over their visits.
 constexpr int count_slices_per_wave(int ch) { return 64 / ch < 8 ? 64 / ch : 8; }
-constexpr int kPrefetch = 4;  // alpha entries per thread carried to the next visit
+// alpha and beta entries per thread carried to the next visit (512 threads
+// cover the destinations of a trigram tagger's label in one round)
+constexpr int count_prefetch(int nt) { return nt >= 512 ? 1 : 2; }
 
-template <int NT>
-__device__ __forceinline__ void fetch_alpha(const DevLayout &fl, const TapeView &tp, const VisitInfo &vi,
-                                            int32_t start, int tid, int (&key)[kPrefetch],
-                                            float (&val)[kPrefetch])
+template <int PF>
+struct VisitVals {
+    int key[PF];    // alpha_{t-1}: state (-1: none)
+    float aval[PF];
+    float bval[PF]; // (beta~_t[j] - b_max) + offset for j = tid + u * NT
+};
+
+template <int NT, int PF = count_prefetch(NT)>
+__device__ __forceinline__ void fetch_visit(const DevLayout &fl, const TapeView &tp, const VisitInfo &vi,
+                                            int32_t start, int n_dst, int tid, VisitVals<PF> &x)
 {
+    constexpr int kPrefetch = PF;
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) key[u] = -1;
+    for (int u = 0; u < kPrefetch; ++u) x.key[u] = -1;
     if (!vi.live) return;
+    const float *tb = tp.beta + vi.b_off;
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+        const int j = tid + u * NT;
+        if (j < n_dst) x.bval[u] = (tb[j] - vi.bm) + vi.o;
+    }
     if (vi.prev_label < 0) {
         if (tid == 0) {
-            key[0] = start;
-            val[0] = 0.0f;
+            x.key[0] = start;
+            x.aval[0] = 0.0f;
         }
         return;
     }
@@ -729,8 +746,8 @@ __device__ __forceinline__ void fetch_alpha(const DevLayout &fl, const TapeView 
     for (int u = 0; u < kPrefetch; ++u) {
         const int j = tid + u * NT;
         if (j < lp.n_segs) {
-            key[u] = fl.seg_key[lp.seg_first + j];
-            val[u] = ta[j] - vi.cm;
+            x.key[u] = fl.seg_key[lp.seg_first + j];
+            x.aval[u] = ta[j] - vi.cm;
         }
     }
 }
@@ -739,19 +756,21 @@ template <int NT, int CH>
 __global__ void __launch_bounds__(NT)
 counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
               const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
-              const VisitInfo *__restrict__ vinfo, float *__restrict__ grad,
-              float *__restrict__ partial, int32_t *__restrict__ item_slot,
+              int32_t *__restrict__ item_queue, const VisitInfo *__restrict__ vinfo,
+              float *__restrict__ grad, float *__restrict__ partial, int32_t *__restrict__ item_slot,
               int32_t *__restrict__ slot_counter, CountCaps caps)
 {
     constexpr int NW = NT / 64;
     constexpr int KPP = count_slices_per_wave(CH);
     constexpr int MAXR = KPP * CH;
+    constexpr int kPrefetch = count_prefetch(NT);
     extern __shared__ __align__(16) unsigned char smem[];
     CEnt *den0 = reinterpret_cast<CEnt *>(smem);
     CEnt *den1 = den0 + (Q + 1);
     int32_t *fmap = reinterpret_cast<int32_t *>(den1 + (Q + 1));  // [Q] state -> forward segment of the label
-    int32_t *chunk_seg = fmap + Q;                                 // reverse chunk -> segment (multi-chunk)
-    __shared__ int s_slot;
+    float *bden = reinterpret_cast<float *>(fmap + Q);              // [2][max forward segments]
+    int32_t *chunk_seg = reinterpret_cast<int32_t *>(bden + 2 * fl.max_segs);  // reverse chunk -> segment
+    __shared__ int s_item, s_slot;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -765,7 +784,16 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
         if (blockIdx.x == 0 && tid == 0) atomicOr(bv.health, H_ITEM);
         nit = 0;
     }
-    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    for (int pops = 0;; ++pops) {
+        if (tid == 0) s_item = atomicAdd(item_queue, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= nit) break;
+        if (it < 0 || pops > nit) {
+            if (tid == 0) atomicOr(bv.health, H_QUEUE);
+            break;
+        }
         const CountItem ci = items[it];
         if (ci.first < 0 || ci.last < ci.first || (int64_t)ci.last > bv.N || ci.last - ci.first > caps.V ||
             ci.label < 0 || ci.label >= bv.M) {
@@ -774,7 +802,10 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
         }
         const LabelInfo li = rl.label[ci.label];
         const LabelInfo lf = fl.label[ci.label];
-        __syncthreads();
+        if (lf.n_segs > fl.max_segs) {
+            if (tid == 0) atomicOr(bv.health, H_ITEM);
+            continue;
+        }
         for (int j = tid; j < lf.n_segs; j += NT) fmap[fl.seg_key[lf.seg_first + j]] = j;
         for (int j = tid; j < li.n_multi; j += NT) {
             const SegChunk sc = rl.seg_chunk[li.seg_first + j];
@@ -792,7 +823,7 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
         }
         const int passes = (li.n_slices + NW * KPP - 1) / (NW * KPP);
         for (int pass = 0; pass < passes; ++pass) {
-            __syncthreads();  // the previous pass may still read either density buffer
+            __syncthreads();  // the previous pass may still read the LDS vectors
             float acc[MAXR];
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) acc[r] = 0.0f;
@@ -811,27 +842,33 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
                 }
             }
             VisitInfo vi = vinfo[ci.first];
-            int key[kPrefetch];
-            float val[kPrefetch];
-            fetch_alpha<NT>(fl, tp, vi, start, tid, key, val);
+            VisitVals<kPrefetch> nx;
+            fetch_visit<NT>(fl, tp, vi, start, lf.n_segs, tid, nx);
             for (int v = ci.first; v < ci.last; ++v) {
                 CEnt *den = (v & 1) ? den1 : den0;
+                float *bd = bden + (v & 1) * fl.max_segs;
+                if (vi.live) {
 #pragma unroll
-                for (int u = 0; u < kPrefetch; ++u)
-                    if (key[u] >= 0) den[key[u]] = CEnt{val[u], v};
-                if (vi.live && vi.prev_label >= 0) {  // rare: more alpha entries than NT * kPrefetch
-                    const LabelInfo lp = fl.label[vi.prev_label];
-                    for (int j = tid + kPrefetch * NT; j < lp.n_segs; j += NT)
-                        den[fl.seg_key[lp.seg_first + j]] = CEnt{tp.alpha[vi.a_off + j] - vi.cm, v};
+                    for (int u = 0; u < kPrefetch; ++u) {
+                        if (nx.key[u] >= 0) den[nx.key[u]] = CEnt{nx.aval[u], v};
+                        if (tid + u * NT < lf.n_segs) bd[tid + u * NT] = nx.bval[u];
+                    }
+                    // rare: more entries than NT * kPrefetch
+                    for (int j = tid + kPrefetch * NT; j < lf.n_segs; j += NT)
+                        bd[j] = (tp.beta[vi.b_off + j] - vi.bm) + vi.o;
+                    if (vi.prev_label >= 0) {
+                        const LabelInfo lp = fl.label[vi.prev_label];
+                        for (int j = tid + kPrefetch * NT; j < lp.n_segs; j += NT)
+                            den[fl.seg_key[lp.seg_first + j]] = CEnt{tp.alpha[vi.a_off + j] - vi.cm, v};
+                    }
                 }
                 const VisitInfo cur = vi;
-                if (v + 1 < ci.last) {  // next visit's record and alpha, in flight during this one
+                if (v + 1 < ci.last) {  // next visit's record, alpha and beta, in flight during this one
                     vi = vinfo[v + 1];
-                    fetch_alpha<NT>(fl, tp, vi, start, tid, key, val);
+                    fetch_visit<NT>(fl, tp, vi, start, lf.n_segs, tid, nx);
                 }
                 __syncthreads();
                 if (!cur.live) continue;
-                const float *tb = tp.beta + cur.b_off;
 #pragma unroll
                 for (int k = 0; k < KPP; ++k) {
                     float a = WFST_NINF;
@@ -841,8 +878,7 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
                     }
                     const bool live = a != WFST_NINF;
                     if (__ballot(live) != 0ull && live) {
-                        const int s = (pass * KPP + k) * NW + wave;
-                        const SliceInfo si = rl.slice[li.slice_first + s];
+                        const SliceInfo si = rl.slice[li.slice_first + (pass * KPP + k) * NW + wave];
                         const int32_t *op = rl.other + si.base + lane;
                         const float *sp = rl.score + si.base + lane;
 #pragma unroll
@@ -850,8 +886,7 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
                             if (r < si.height) {
                                 const Elem e{op[r * si.width], sp[r * si.width]};
                                 if (e.other < Q) {
-                                    const float bh = (tb[fmap[e.other]] - cur.bm) + cur.o;
-                                    const float x = (a + e.score) + bh;
+                                    const float x = (a + e.score) + bd[fmap[e.other]];
                                     acc[k * CH + r] += cur.g * exp_e(x);
                                 }
                             }
@@ -863,20 +898,18 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
 #pragma unroll
             for (int k = 0; k < KPP; ++k) {
                 const int s = (pass * KPP + k) * NW + wave;
-                if (s < li.n_slices) {
-                    const SliceInfo si = rl.slice[li.slice_first + s];
-                    if (lane < si.width) {
+                const SliceInfo si = s < li.n_slices ? rl.slice[li.slice_first + s] : SliceInfo{0, 0, 0, 0};
+                if (lane < si.width) {
 #pragma unroll
-                        for (int r = 0; r < CH; ++r) {
-                            if (r < si.height) {
-                                const int pos = si.base + r * si.width + lane;
-                                const float val2 = acc[k * CH + r];
-                                if (slot == -1) {
-                                    const int arc = rl.elem_arc[pos];
-                                    if (arc >= 0) grad[arc] = val2;
-                                } else if (slot >= 0) {
-                                    partial[(int64_t)slot * rl.max_elems + (pos - li.elem_first)] = val2;
-                                }
+                    for (int r = 0; r < CH; ++r) {
+                        if (r < si.height) {
+                            const int pos = si.base + r * si.width + lane;
+                            const float val2 = acc[k * CH + r];
+                            if (slot == -1) {
+                                const int arc = rl.elem_arc[pos];
+                                if (arc >= 0) grad[arc] = val2;
+                            } else if (slot >= 0) {
+                                partial[(int64_t)slot * rl.max_elems + (pos - li.elem_first)] = val2;
                             }
                         }
                     }

@@ -94,7 +94,7 @@ enum WsSlot {
 };
 
 // small device counters kept together (one allocation)
-enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_TOTAL = 4 /* int64 at byte 16 */,
+enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_ITEMQ = 3, C_TOTAL = 4 /* int64 at byte 16 */,
                C_SETOTAL = 6 /* int64 at byte 24 */, C_COUNT = 8 };
 
 struct TapeBufs {
@@ -240,7 +240,7 @@ size_t lds_lse(const wfst_fst *f, const DevLayout &l)
 size_t lds_counts(const wfst_fst *f)
 {
     return (size_t)(f->Q + 1) * 2 * sizeof(CEnt) + (size_t)f->Q * sizeof(int32_t) +
-           (size_t)std::max(f->rev.max_slots, 1) * sizeof(int32_t);
+           (size_t)2 * f->fwd.max_segs * sizeof(float) + (size_t)std::max(f->rev.max_slots, 1) * sizeof(int32_t);
 }
 
 template <class K>
@@ -365,15 +365,16 @@ int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const
 
 template <int NT, int CH>
 int launch_counts_nt(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
-                     const CountItem *items, const int32_t *n_items, int64_t items_bound, const VisitInfo *vinfo,
-                     float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter, CountCaps caps)
+                     const CountItem *items, const int32_t *n_items, int32_t *item_queue, int64_t items_bound,
+                     const VisitInfo *vinfo, float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter,
+                     CountCaps caps)
 {
     const size_t lds = lds_counts(f);
     int grid = 0;
     TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
     ProfScope prof(f, s, WFST_KERNEL_COUNTS);
     hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start, bv,
-                       tp, items, n_items, vinfo, grad, partial, item_slot, slot_counter, caps);
+                       tp, items, n_items, item_queue, vinfo, grad, partial, item_slot, slot_counter, caps);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -382,18 +383,19 @@ int launch_counts_nt(const wfst_fst *f, hipStream_t s, const BatchView &bv, cons
 // of the reverse layout to fit one pass (KPP = 64 / CH slices per wavefront).
 template <int CH>
 int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
-                     const CountItem *items, const int32_t *n_items, int64_t items_bound, const VisitInfo *vinfo,
-                     float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter, CountCaps caps)
+                     const CountItem *items, const int32_t *n_items, int32_t *item_queue, int64_t items_bound,
+                     const VisitInfo *vinfo, float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter,
+                     CountCaps caps)
 {
     constexpr int KPP = count_slices_per_wave(CH);
     const int waves = (f->rev.max_slices + KPP - 1) / KPP;
     if (waves > 8)
-        return launch_counts_nt<1024, CH>(f, s, bv, tp, items, n_items, items_bound, vinfo, grad, partial,
+        return launch_counts_nt<1024, CH>(f, s, bv, tp, items, n_items, item_queue, items_bound, vinfo, grad, partial,
                                           item_slot, slot_counter, caps);
     if (waves > 4)
-        return launch_counts_nt<512, CH>(f, s, bv, tp, items, n_items, items_bound, vinfo, grad, partial,
+        return launch_counts_nt<512, CH>(f, s, bv, tp, items, n_items, item_queue, items_bound, vinfo, grad, partial,
                                          item_slot, slot_counter, caps);
-    return launch_counts_nt<256, CH>(f, s, bv, tp, items, n_items, items_bound, vinfo, grad, partial, item_slot,
+    return launch_counts_nt<256, CH>(f, s, bv, tp, items, n_items, item_queue, items_bound, vinfo, grad, partial, item_slot,
                                      slot_counter, caps);
 }
 
@@ -901,19 +903,19 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
                        (const int32_t *)tok_sent, grad_log_z, vinfo);
     const int ch = f->rev.max_height;  // slice height bound of the reverse layout
     if (ch <= 4)
-        rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+        rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
                                  partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 8)
-        rc = launch_counts_ch<8>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+        rc = launch_counts_ch<8>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
                                  partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 16)
-        rc = launch_counts_ch<16>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+        rc = launch_counts_ch<16>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
                                   partial, item_slot, counters + C_SLOTS, caps);
     else if (ch <= 32)
-        rc = launch_counts_ch<32>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+        rc = launch_counts_ch<32>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
                                   partial, item_slot, counters + C_SLOTS, caps);
     else
-        rc = launch_counts_ch<64>(f, s, bv, tp, items, counters + C_NITEMS, items_bound, vinfo, grad_arc_score,
+        rc = launch_counts_ch<64>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
                                   partial, item_slot, counters + C_SLOTS, caps);
     if (rc != WFST_OK) return rc;
     // labels split over several items: one thread per (label, element) sums the partials
