@@ -293,29 +293,34 @@ def forward(fst: Fst, offsets, tokens):
     return log_z, status, Tape(fst, h, (off, tok, status))
 
 
-def backward(fst: Fst, tape: Tape, grad_log_z=None):
-    """d(sum_b g_b log Z_b)/d arc_score as a float32 device tensor [num_arcs]."""
+def backward(fst: Fst, tape: Tape, grad_log_z=None, final=False):
+    """d(sum_b g_b log Z_b)/d arc_score as a float32 device tensor [num_arcs];
+    with final=True also d(...)/d final_score [num_states]: (grad, grad_final)."""
     import torch
     if tape._h is None:
         raise WfstError(WFST_EINVAL, "tape already freed")
-    grad = torch.empty(fst.num_arcs, dtype=torch.float32, device=tape._keep[0].device)
+    dev = tape._keep[0].device
+    grad = torch.empty(fst.num_arcs, dtype=torch.float32, device=dev)
+    gfin = torch.empty(fst.num_states, dtype=torch.float32, device=dev) if final else None
     g = None
     if grad_log_z is not None:
         g = grad_log_z.to(dtype=torch.float32).contiguous()
-    _check(_lib.wfst_backward(fst.handle, tape._h, _dptr(g), _dptr(grad), None, _stream()))
-    return grad
+    _check(_lib.wfst_backward(fst.handle, tape._h, _dptr(g), _dptr(grad), _dptr(gfin), _stream()))
+    return (grad, gfin) if final else grad
 
 
-def forward_backward(fst: Fst, offsets, tokens):
-    """(log_z f32[B], arc_posterior f32[num_arcs] summed over the batch, status i32[B])."""
+def forward_backward(fst: Fst, offsets, tokens, final_posteriors=False):
+    """(log_z f32[B], arc_posterior f32[num_arcs] summed over the batch, status i32[B]);
+    with final_posteriors=True, (log_z, arc_posterior, final_posterior f32[num_states], status)."""
     import torch
     off, tok, B, N = _batch(offsets, tokens)
     log_z = torch.empty(B, dtype=torch.float32, device=off.device)
     post = torch.empty(fst.num_arcs, dtype=torch.float32, device=off.device)
+    fpost = torch.empty(fst.num_states, dtype=torch.float32, device=off.device) if final_posteriors else None
     status = torch.empty(B, dtype=torch.int32, device=off.device)
     _check(_lib.wfst_forward_backward(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(log_z),
-                                      _dptr(post), None, _dptr(status), _stream()))
-    return log_z, post, status
+                                      _dptr(post), _dptr(fpost), _dptr(status), _stream()))
+    return (log_z, post, fpost, status) if final_posteriors else (log_z, post, status)
 
 
 def _make_log_partition():
@@ -330,18 +335,23 @@ def _make_log_partition():
         """
 
         @staticmethod
-        def forward(ctx, arc_score, fst, offsets, tokens):
-            fst.set_scores(arc_score.detach().contiguous())
+        def forward(ctx, arc_score, fst, offsets, tokens, final_score=None):
+            fst.set_scores(arc_score.detach().contiguous(),
+                           None if final_score is None else final_score.detach().contiguous())
             log_z, status, tape = forward(fst, offsets, tokens)
             ctx.fst, ctx.tape = fst, tape
+            ctx.final = final_score is not None and final_score.requires_grad
             ctx.mark_non_differentiable(status)
             return log_z, status
 
         @staticmethod
         def backward(ctx, grad_log_z, _grad_status):
-            g = backward(ctx.fst, ctx.tape, grad_log_z)
+            if ctx.final:
+                g, gf = backward(ctx.fst, ctx.tape, grad_log_z, final=True)
+            else:
+                g, gf = backward(ctx.fst, ctx.tape, grad_log_z), None
             ctx.tape.free()
-            return g, None, None, None
+            return g, None, None, None, gf
 
     return LogPartition
 
@@ -358,6 +368,8 @@ class _Lazy:
 LogPartition = _Lazy()
 
 
-def log_partition(arc_score, fst, offsets, tokens):
-    """Differentiable log Z per sentence (returns (log_z, status))."""
-    return LogPartition.apply(arc_score, fst, offsets, tokens)
+def log_partition(arc_score, fst, offsets, tokens, final_score=None):
+    """Differentiable log Z per sentence (returns (log_z, status)); when
+    final_score (f32[num_states], device) is given it is written into the FST
+    too and receives the final-state posteriors as its gradient."""
+    return LogPartition.apply(arc_score, fst, offsets, tokens, final_score)

@@ -971,6 +971,79 @@ counts_fixup(DevLayout fl, const int32_t *__restrict__ item_base, const int32_t 
     }
 }
 
+// Final-state posteriors (gradient of log Z with respect to the final scores,
+// the f-vector of Eq. 1): P_b(path ends in q) = alpha_T[q] f[q] / Z_b.  Each
+// sentence of a block writes its nonzero terms into its own dense row (one
+// wavefront per sentence, rows zero-filled beforehand); rows are summed per
+// state in sentence order, in groups and then over groups.
+__global__ void final_rows(BatchView bv, TapeView tp, DevLayout fl, int32_t Q, int32_t start,
+                           const float *__restrict__ final_score, const float *__restrict__ grad_log_z,
+                           int32_t b0, int32_t nb, float *__restrict__ rows)
+{
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x / 64;
+    for (int bb = blockIdx.x * wpb + (threadIdx.x >> 6); bb < nb; bb += gridDim.x * wpb) {
+        const int b = b0 + bb;
+        if (bv.status[b] != WFST_STATUS_OK) continue;
+        const int o0 = bv.offsets[b], o1 = bv.offsets[b + 1];
+        if (o0 < 0 || o1 < o0 || (int64_t)o1 > bv.N) {
+            if (lane == 0) atomicOr(bv.health, H_VISIT);
+            continue;
+        }
+        const float g = grad_log_z ? grad_log_z[b] : 1.0f;
+        float *row = rows + (int64_t)bb * Q;
+        if (o1 == o0) {  // empty sentence: the path ends where it starts
+            if (lane == 0) {
+                const float f = final_score[start];
+                if (f != WFST_NINF) row[start] = g * exp_e((0.0f + f) + (float)(0.0 - tp.log_z[b]));
+            }
+            continue;
+        }
+        const int i = o1 - 1;
+        const int a = bv.tokens[i];
+        if (a < 0 || a >= bv.M) {
+            if (lane == 0) atomicOr(bv.health, H_VISIT);
+            continue;
+        }
+        const LabelInfo lf = fl.label[a];
+        const float *ta = tp.alpha + bv.tok_off[i];
+        const float c = tp.a_max[i];
+        const float o = (float)(tp.a_log[i] - tp.log_z[b]);
+        for (int j = lane; j < lf.n_segs; j += 64) {
+            const int q = fl.seg_key[lf.seg_first + j];
+            const float x = ta[j], f = final_score[q];
+            if (x == WFST_NINF || f == WFST_NINF) continue;
+            row[q] = g * exp_e(((x - c) + f) + o);
+        }
+    }
+}
+
+// S[g][q] = sum of rows[b][q] over the G rows of group g, in row order
+__global__ void sum_row_groups(const float *__restrict__ rows, int32_t nb, int32_t Q, int32_t G,
+                               float *__restrict__ S)
+{
+    const int32_t ng = (nb + G - 1) / G;
+    const int64_t n = (int64_t)ng * Q;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(w / Q), q = (int)(w % Q);
+        const int b1 = min(nb, (g + 1) * G);
+        float s = 0.0f;
+        for (int b = g * G; b < b1; ++b) s += rows[(int64_t)b * Q + q];
+        S[w] = s;
+    }
+}
+
+// out[q] (+)= sum over groups g of S[g][q], in group order
+__global__ void sum_groups(const float *__restrict__ S, int32_t ng, int32_t Q, int32_t accumulate,
+                           float *__restrict__ out)
+{
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < Q; q += gridDim.x * blockDim.x) {
+        float s = accumulate ? out[q] : 0.0f;
+        for (int g = 0; g < ng; ++g) s += S[(int64_t)g * Q + q];
+        out[q] = s;
+    }
+}
+
 // element count of every label whose visits span several count work items
 __global__ void split_label_elems(const LabelInfo *__restrict__ label, const int32_t *__restrict__ n_items_label,
                                   int32_t M, int32_t *__restrict__ out)

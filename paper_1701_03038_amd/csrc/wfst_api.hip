@@ -90,7 +90,7 @@ int ensure_t(Buf &b, int64_t count, hipStream_t s, T **out)
 enum WsSlot {
     W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
-    W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_NUM
+    W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_NUM
 };
 
 // small device counters kept together (one allocation)
@@ -459,6 +459,46 @@ int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, co
     HIP_OK(hipGetLastError());
     *skeys_out = k0;
     *visits_out = v0;
+    return WFST_OK;
+}
+
+// d(sum_b g_b log Z_b)/d final_score into out[Q], from the forward tape.
+int final_posteriors(wfst_fst *f, const wfst_tape *tape, const float *grad_log_z, float *out, hipStream_t s)
+{
+    const int32_t Q = f->Q, B = tape->B;
+    constexpr int32_t G = 64;
+    if (B == 0) {
+        hipLaunchKernelGGL(fill_f32, dim3(grid_for(Q, 256)), dim3(256), 0, s, out, (int64_t)Q, 0.0f);
+        HIP_OK(hipGetLastError());
+        return WFST_OK;
+    }
+    // sentences per block: dense rows of at most 256 MiB
+    int64_t nb_max = ((int64_t)256 << 20) / ((int64_t)Q * (int64_t)sizeof(float));
+    nb_max = std::max<int64_t>(G, nb_max / G * G);
+    nb_max = std::min<int64_t>(nb_max, B);
+    float *rows, *S;
+    TRY(ensure_t(f->ws[W_FROWS], nb_max * Q, s, &rows));
+    TRY(ensure_t(f->ws[W_FSUM], (nb_max + G - 1) / G * Q, s, &S));
+    TapeView tp;
+    tp.alpha = tape->alpha;
+    tp.a_max = tape->a_max;
+    tp.a_log = tape->a_log;
+    tp.log_z = tape->log_z;
+    const BatchView bv = make_view(f, B, tape->N, tape->offsets, tape->tokens, tape->order, tape->tok_off, nullptr,
+                                   tape->status);
+    for (int64_t b0 = 0; b0 < B; b0 += nb_max) {
+        const int32_t nb = (int32_t)std::min<int64_t>(nb_max, B - b0);
+        const int32_t ng = (nb + G - 1) / G;
+        hipLaunchKernelGGL(fill_f32, dim3(grid_for((int64_t)nb * Q, 256, 8192)), dim3(256), 0, s, rows,
+                           (int64_t)nb * Q, 0.0f);
+        hipLaunchKernelGGL(final_rows, dim3(grid_for(nb, 4)), dim3(256), 0, s, bv, tp, f->fwd, Q, f->start,
+                           (const float *)f->final_score, grad_log_z, (int32_t)b0, nb, rows);
+        hipLaunchKernelGGL(sum_row_groups, dim3(grid_for((int64_t)ng * Q, 256, 16384)), dim3(256), 0, s,
+                           (const float *)rows, nb, Q, G, S);
+        hipLaunchKernelGGL(sum_groups, dim3(grid_for(Q, 256)), dim3(256), 0, s, (const float *)S, ng, Q,
+                           (int32_t)(b0 > 0), out);
+    }
+    HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 
@@ -835,9 +875,9 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     if (!fc || !tape) return set_err(WFST_EINVAL, "NULL fst or tape");
     if (tape->fst != fc) return set_err(WFST_EINVAL, "tape belongs to another FST");
     if (!grad_arc_score && fc->A > 0) return set_err(WFST_EINVAL, "grad_arc_score is NULL");
-    if (grad_final) return set_err(WFST_EUNSUPPORTED, "grad_final is not supported by this build");
     wfst_fst *f = const_cast<wfst_fst *>(fc);
     hipStream_t s = as_stream(stream);
+    if (grad_final) TRY(final_posteriors(f, tape, grad_log_z, grad_final, s));
     if (f->A > 0) {
         ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
         hipLaunchKernelGGL(fill_f32, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s, grad_arc_score, f->A, 0.0f);

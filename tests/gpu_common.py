@@ -61,3 +61,41 @@ def assert_fb_parity(fst, batch, fst_dev, ctx="", per_sentence_tol=False):
                                    f"(n_k={n_k[worst]}, gpu={post[worst]}, oracle={opost[worst]})")
     assert not np.any(np.isnan(post))
     return lz, post, st
+
+
+def final_visits(fst, batch):
+    """n_q: number of sentences whose last step can end in state q (the
+    destinations of the last token's label; the start state for an empty one)."""
+    n = np.zeros(fst.num_states, np.float64)
+    last = {}
+    for b in range(batch.size):
+        o0, o1 = int(batch.offsets[b]), int(batch.offsets[b + 1])
+        if o1 == o0:
+            n[fst.start] += 1
+            continue
+        a = int(batch.tokens[o1 - 1])
+        if not 0 <= a < fst.num_ilabels:
+            continue
+        if a not in last:
+            last[a] = np.unique(fst.dst[fst.ilabel == a])
+        n[last[a]] += 1
+    return n
+
+
+def assert_final_parity(fst, batch, fst_dev, ctx=""):
+    """Batch-summed final-state posteriors within 1e-5 per sentence that can end there."""
+    import torch
+    import paper_1701_03038_amd as wf
+    lz, post, fpost, st = wf.forward_backward(fst_dev, batch.offsets, batch.tokens, final_posteriors=True)
+    torch.cuda.synchronize()
+    assert fst_dev.health() == 0, f"kernel health flags {fst_dev.health():#x}"
+    fpost = fpost.cpu().numpy().astype(np.float64)
+    _, _, ofpost, ost = oracle.forward_backward(fst, batch, arc_posteriors=False, final_posteriors=True)
+    np.testing.assert_array_equal(st.cpu().numpy(), ost, err_msg=f"status {ctx}")
+    bound = 1e-5 * np.maximum(1.0, final_visits(fst, batch))
+    err = np.abs(fpost - ofpost)
+    worst = int(np.argmax(err / bound))
+    assert np.all(err <= bound), f"{ctx}: final posterior err {err[worst]:.3g} at state {worst}"
+    n_ok = int(np.sum(ost == oracle.ST_OK))
+    assert abs(fpost.sum() - n_ok) <= 1e-5 * max(1, n_ok)
+    return fpost

@@ -11,7 +11,7 @@ import pytest
 import oracle
 import synth
 from conftest import fig1_fst
-from gpu_common import assert_fb_parity, say, visits_per_arc
+from gpu_common import assert_fb_parity, assert_final_parity, final_visits, say, visits_per_arc
 
 pytestmark = pytest.mark.gpu
 
@@ -171,3 +171,44 @@ def test_set_scores_roundtrip(wf):
     f2 = synth.Fst(**{**fst.__dict__})
     f2.arc_score = new
     assert_fb_parity(f2, batch, d, "set_scores")
+
+
+def test_final_posteriors(wf):
+    """Gradient with respect to the final scores (final-state posteriors)."""
+    for seed in range(4):
+        say(f"case: final posteriors tiny seed={seed}")
+        fst = synth.tiny_random_fst(seed, 3 + seed, 2 + seed % 2, 12 + 3 * seed, final_prob=0.6)
+        lens = np.random.default_rng(seed).integers(0, 7, 40)
+        batch = synth.random_batch(seed, fst.num_ilabels, lens)
+        d = wf.Fst.from_synth(fst)
+        assert_final_parity(fst, batch, d, f"tiny seed={seed}")
+    say("case: final posteriors fig1 edge cases")
+    g, fst, _ = fig1_fst()
+    d = wf.Fst.from_synth(fst)
+    batch = synth.Batch(np.array([0, 2, 4, 4, 7], np.int64), np.array([1, 0, 0, 7, 0, 1, 2], np.int32))
+    assert_final_parity(fst, batch, d, "fig1 edge")
+    say("case: final posteriors trigram small")
+    fst, batch = synth.config(3, vocab=1000, batch=96)
+    d = wf.Fst.from_synth(fst)
+    assert_final_parity(fst, batch, d, "trigram small")
+
+
+def test_autograd_final_scores(wf):
+    """log_partition with final scores as a parameter: its gradient is
+    sum_b g_b P_b(path ends in q) (FP64 oracle)."""
+    import torch
+    fst = synth.tiny_random_fst(5, 6, 3, 30, final_prob=0.7)
+    batch = synth.random_batch(5, fst.num_ilabels, np.random.default_rng(5).integers(0, 8, 50))
+    d = wf.Fst.from_synth(fst)
+    theta = torch.tensor(fst.arc_score, device="cuda", requires_grad=True)
+    fin = torch.tensor(fst.final_score, device="cuda", requires_grad=True)
+    g = torch.linspace(0.5, 1.5, batch.size, device="cuda")
+    lz, st = wf.log_partition(theta, d, batch.offsets, batch.tokens, final_score=fin)
+    ok = st == 0
+    (torch.where(ok, lz, torch.zeros_like(lz)) * g).sum().backward()
+    gn = (g * ok).cpu().numpy().astype(np.float64)
+    _, ograd, ofin, _ = oracle.forward_backward(fst, batch, grad_log_z=gn, final_posteriors=True)
+    n_k = visits_per_arc(fst, batch)
+    assert np.all(np.abs(theta.grad.cpu().numpy() - ograd) <= 1e-5 * np.maximum(1, n_k))
+    nf = final_visits(fst, batch)
+    assert np.all(np.abs(fin.grad.cpu().numpy() - ofin) <= 1e-5 * np.maximum(1, nf))
