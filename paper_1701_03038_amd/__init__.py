@@ -146,7 +146,7 @@ class Fst:
     """Device layouts of one WFST (library-owned; freed by close())."""
 
     def __init__(self, num_states, num_ilabels, start, src, dst, ilabel, arc_score, final_score,
-                 olabel=None, chunk_arcs=0, threads_per_sentence=0):
+                 olabel=None, chunk_arcs=0, threads_per_sentence=0, checkpoint=0, tape_budget_bytes=0):
         import torch
         lib = load_library()
         self.num_states, self.num_ilabels, self.start = int(num_states), int(num_ilabels), int(start)
@@ -155,7 +155,7 @@ class Fst:
         sc = np.ascontiguousarray(arc_score, np.float32)
         fin = np.ascontiguousarray(final_score, np.float32)
         self.num_arcs = int(arrs[0].shape[0])
-        opt = _Options(chunk_arcs, threads_per_sentence, 0, 0, 0, 0)
+        opt = _Options(chunk_arcs, threads_per_sentence, checkpoint, 0, tape_budget_bytes, 0)
         self.device = torch.cuda.current_device()
         h = ctypes.c_void_p()
         _check(lib.wfst_fst_create(self.num_states, self.num_ilabels, self.start, self.num_arcs,

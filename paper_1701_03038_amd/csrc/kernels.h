@@ -61,6 +61,38 @@ struct TapeView {
     double *b_log = nullptr;   // [N]
     double *log_z = nullptr;   // [B]
     double *log_z_bwd = nullptr;  // [B] log Z recomputed from beta_0[start]
+    const int64_t *ck_off = nullptr;  // checkpointed tape: alpha~ offset per token (-1: not kept); null = all kept
 };
+
+// Checkpointed forward-backward: alpha~ is kept only every c steps (and at
+// the last step); the backward pass walks blocks of c steps from the end,
+// recomputing each block's alpha~ from its checkpoint.  A block's alpha~ and
+// beta~ live in double buffers chosen by block parity, at a per-sentence base
+// plus the token's offset inside its block.
+struct BlockView {
+    int32_t c = 0;  // checkpoint interval; 0 = the whole tape is resident
+    int32_t k = 0;  // block being processed: steps k*c+1 .. (k+1)*c
+    float *abuf[2] = {nullptr, nullptr};
+    float *bbuf[2] = {nullptr, nullptr};
+    const int64_t *base = nullptr;  // [B]
+};
+
+// Offset of token i (sentence b starting at o0) inside its block buffer.
+__device__ __forceinline__ int64_t block_rel(const BlockView &bk, const BatchView &bv, int b, int o0, int i,
+                                             int &blk)
+{
+    blk = (i - o0) / bk.c;  // step i - o0 + 1 lies in block (step - 1) / c
+    return bk.base[b] + (bv.tok_off[i] - bv.tok_off[o0 + blk * bk.c]);
+}
+
+// beta~ of token i: the full tape, or the block buffer of the token's block
+__device__ __forceinline__ float *beta_slot(const TapeView &tp, const BlockView &bk, const BatchView &bv, int b,
+                                            int o0, int i)
+{
+    if (bk.c == 0) return tp.beta + bv.tok_off[i];
+    int blk;
+    const int64_t r = block_rel(bk, bv, b, o0, i, blk);
+    return bk.bbuf[blk & 1] + r;
+}
 
 }  // namespace wfst

@@ -426,7 +426,7 @@ __device__ __forceinline__ void block_max_into(float v, uint32_t *cell, int lane
 template <int NT>
 __global__ void __launch_bounds__(NT)
 forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ final_score,
-              BatchView bv, TapeView tp, float *__restrict__ log_z_out)
+              BatchView bv, TapeView tp, BlockView bk, float *__restrict__ log_z_out)
 {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -453,14 +453,25 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
         }
         const int b = bv.order[item];
         int o0, o1;
-        const int st = check_sentence<NT>(bv, b, o0, o1);
-        if (st != WFST_STATUS_OK) {
-            if (tid == 0) {
-                bv.status[b] = st;
-                log_z_out[b] = WFST_NINF;
-                tp.log_z[b] = -__builtin_huge_val();
+        int t0 = 0, t1 = 0;  // steps t0+1 .. t1
+        if (bk.c == 0) {
+            const int st = check_sentence<NT>(bv, b, o0, o1);
+            if (st != WFST_STATUS_OK) {
+                if (tid == 0) {
+                    bv.status[b] = st;
+                    log_z_out[b] = WFST_NINF;
+                    tp.log_z[b] = -__builtin_huge_val();
+                }
+                continue;
             }
-            continue;
+            t1 = o1 - o0;
+        } else {  // recompute one block of alpha~ from its checkpoint
+            if (bv.status[b] != WFST_STATUS_OK) continue;
+            o0 = bv.offsets[b];
+            o1 = bv.offsets[b + 1];
+            t0 = bk.k * bk.c;
+            t1 = min(o1 - o0, t0 + bk.c);
+            if (t1 <= t0) continue;
         }
         const int T = o1 - o0;
         for (int q = tid; q <= Q; q += NT) {
@@ -469,16 +480,35 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
         }
         if (tid < 3) s_cmax[tid] = 0u;
         __syncthreads();
-        if (tid == 0) val0[start] = 0.0f;
-        __syncthreads();
         float c_prev = 0.0f;
+        {
+            float *first = ((t0 + 1) & 1) ? val0 : val1;
+            if (t0 == 0) {
+                if (tid == 0) first[start] = 0.0f;
+            } else {
+                const int ic = o0 + t0 - 1;
+                const LabelInfo lc = fl.label[bv.tokens[ic]];
+                const float *ta = tp.alpha + tp.ck_off[ic];
+                for (int j = tid; j < lc.n_segs; j += NT) first[fl.seg_key[lc.seg_first + j]] = ta[j];
+                c_prev = tp.a_max[ic];
+            }
+        }
+        __syncthreads();
         double C = 0.0;  // log scale of alpha (thread 0)
-        for (int t = 1; t <= T; ++t) {
+        for (int t = t0 + 1; t <= t1; ++t) {
             float *prev = (t & 1) ? val0 : val1;
             float *cur = (t & 1) ? val1 : val0;
             const int i = o0 + t - 1;
             const LabelInfo li = fl.label[bv.tokens[i]];
-            float *tape = tp.alpha + bv.tok_off[i];
+            float *tape;
+            if (bk.c > 0) {
+                int blk;
+                tape = bk.abuf[bk.k & 1] + block_rel(bk, bv, b, o0, i, blk);
+            } else if (tp.ck_off) {
+                tape = tp.ck_off[i] >= 0 ? tp.alpha + tp.ck_off[i] : nullptr;
+            } else {
+                tape = tp.alpha + bv.tok_off[i];
+            }
             const float mx = lse_step<NT, 1, kRowBatch>(fl, li, prev, cur, c_prev, part, tape, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
@@ -491,12 +521,16 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             __syncthreads();
             float c = unord_f32(s_cmax[t % 3]);
             if (!(c > WFST_NINF)) c = 0.0f;
-            if (tid == 0) {
+            if (tid == 0 && bk.c == 0) {
                 C += (double)c;
                 tp.a_max[i] = c;
                 tp.a_log[i] = C;
             }
             c_prev = c;
+        }
+        if (bk.c > 0) {
+            __syncthreads();
+            continue;
         }
         // log Z = C_T + LSE_q(alpha^_T[q] + f[q])
         Lse acc{WFST_NINF, 0.0f};
@@ -541,7 +575,7 @@ template <int NT>
 __global__ void __launch_bounds__(NT)
 backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                const float *__restrict__ final_score, const float *__restrict__ final_max,
-               BatchView bv, TapeView tp)
+               BatchView bv, TapeView tp, BlockView bk)
 {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -571,37 +605,58 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         const int o0 = bv.offsets[b], o1 = bv.offsets[b + 1];
         const int T = o1 - o0;
         if (T == 0) {
-            if (tid == 0) tp.log_z_bwd[b] = (double)final_score[start];
+            if (tid == 0 && bk.k == 0) tp.log_z_bwd[b] = (double)final_score[start];
             continue;
         }
-        float *vT = (T & 1) ? val1 : val0;
-        float *vO = (T & 1) ? val0 : val1;
-        for (int q = tid; q <= Q; q += NT) {
-            vT[q] = q < Q ? final_score[q] : WFST_NINF;
-            vO[q] = WFST_NINF;
+        int t0 = 0, t1 = T;  // steps t1 down to t0+1
+        if (bk.c > 0) {
+            t0 = bk.k * bk.c;
+            t1 = min(T, t0 + bk.c);
+            if (t1 <= t0) continue;
         }
-        if (tid < 3) s_cmax[tid] = 0u;
-        __syncthreads();
-        // beta_T on the destinations of w_T, for the expected counts
-        {
+        float *vT = (t1 & 1) ? val1 : val0;
+        float *vO = (t1 & 1) ? val0 : val1;
+        float c_prev;
+        double C;
+        if (t1 == T) {
+            for (int q = tid; q <= Q; q += NT) {
+                vT[q] = q < Q ? final_score[q] : WFST_NINF;
+                vO[q] = WFST_NINF;
+            }
+            __syncthreads();
+            // beta_T on the destinations of w_T, for the expected counts
             const LabelInfo lf = fl.label[bv.tokens[o1 - 1]];
-            float *tape = tp.beta + bv.tok_off[o1 - 1];
+            float *tape = beta_slot(tp, bk, bv, b, o0, o1 - 1);
             for (int j = tid; j < lf.n_segs; j += NT) tape[j] = vT[fl.seg_key[lf.seg_first + j]];
             if (tid == 0) {
                 tp.b_max[o1 - 1] = fmax0;
                 tp.b_log[o1 - 1] = (double)fmax0;
             }
+            c_prev = fmax0;
+            C = (double)fmax0;
+        } else {  // resume from beta~_{t1} kept by the previous (later) block
+            for (int q = tid; q <= Q; q += NT) {
+                vT[q] = WFST_NINF;
+                vO[q] = WFST_NINF;
+            }
+            __syncthreads();
+            const int i1 = o0 + t1 - 1;
+            const LabelInfo lf = fl.label[bv.tokens[i1]];
+            const float *tape = beta_slot(tp, bk, bv, b, o0, i1);
+            for (int j = tid; j < lf.n_segs; j += NT) vT[fl.seg_key[lf.seg_first + j]] = tape[j];
+            c_prev = tp.b_max[i1];
+            C = tp.b_log[i1];
         }
-        float c_prev = fmax0;
-        double C = (double)fmax0;
-        for (int t = T; t >= 1; --t) {
+        if (tid < 3) s_cmax[tid] = 0u;
+        __syncthreads();
+        for (int t = t1; t > t0; --t) {
             float *prev = (t & 1) ? val1 : val0;  // beta~_t
             float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
             const int i = o0 + t - 1;
             const LabelInfo li = rl.label[bv.tokens[i]];
             const float mx = lse_step<NT, 4, 4>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave, Q);
             const LabelInfo lp = rl.label[bv.tokens[t == T ? i : i + 1]];
-            if (t == T || 4 * lp.n_segs >= Q) {  // wide support: clear the whole vector, no key loads
+            if (t == t1 || 4 * lp.n_segs >= Q) {  // first step or wide support: clear the whole vector
                 for (int q = tid; q < Q; q += NT) prev[q] = WFST_NINF;
             } else {
                 for (int j = tid; j < lp.n_segs; j += NT) prev[rl.seg_key[lp.seg_first + j]] = WFST_NINF;
@@ -614,7 +669,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             if (tid == 0) C += (double)c;
             if (t >= 2) {
                 const LabelInfo lf = fl.label[bv.tokens[i - 1]];
-                float *tape = tp.beta + bv.tok_off[i - 1];
+                float *tape = beta_slot(tp, bk, bv, b, o0, i - 1);
                 for (int j = tid; j < lf.n_segs; j += NT) tape[j] = cur[fl.seg_key[lf.seg_first + j]];
                 if (tid == 0) {
                     tp.b_max[i - 1] = c;
@@ -644,22 +699,24 @@ struct CEnt {
 struct CountItem {
     int32_t first, last;  // range in the label-sorted visit list
     int32_t label;
-    int32_t split;        // 1 when the label's visits span several items
+    int32_t split;        // 1 when its group (label, block) has several items: partial sums + fixup
+    int32_t block;        // checkpoint block of its visits (0 without checkpointing)
+    int32_t carry;        // 1 when the label had items in a block processed earlier: sums continue from grad
 };
 
 // Everything the count kernel needs about one visit (sentence b, step t,
 // token i), in one record: posterior of arc k at this visit is
 //   g * exp((alpha~_{t-1}[src_k] - cm) + score_k + (beta~_t[dst_k] - bm) + o).
 struct VisitInfo {
-    int64_t a_off;       // compact alpha of step t-1 (token i-1)
-    int64_t b_off;       // compact beta of step t (token i)
+    const float *a_ptr;  // compact alpha~ of step t-1 (token i-1)
+    const float *b_ptr;  // compact beta~ of step t (token i)
     int32_t prev_label;  // label of token i-1, -1 at t = 1 (alpha_0 = start)
     int32_t live;        // 0: sentence without a path (or invalid): skip
     float o, cm, bm, g;
 };
 
 // One thread per visit position of the label-sorted list.
-__global__ void visit_table(BatchView bv, TapeView tp, const int32_t *__restrict__ visits,
+__global__ void visit_table(BatchView bv, TapeView tp, BlockView bk, const int32_t *__restrict__ visits,
                             const int32_t *__restrict__ tok_sent, const float *__restrict__ grad_log_z,
                             VisitInfo *__restrict__ out)
 {
@@ -683,8 +740,19 @@ __global__ void visit_table(BatchView bv, TapeView tp, const int32_t *__restrict
             vi.cm = t > 1 ? tp.a_max[i - 1] : 0.0f;
             vi.bm = tp.b_max[i];
             vi.g = grad_log_z ? grad_log_z[b] : 1.0f;
-            vi.a_off = t > 1 ? bv.tok_off[i - 1] : 0;
-            vi.b_off = bv.tok_off[i];
+            vi.a_ptr = nullptr;
+            if (t > 1) {
+                if (bk.c == 0) {
+                    vi.a_ptr = tp.alpha + bv.tok_off[i - 1];
+                } else if (tp.ck_off[i - 1] >= 0) {  // a checkpoint
+                    vi.a_ptr = tp.alpha + tp.ck_off[i - 1];
+                } else {  // recomputed with the visit's block
+                    int blk;
+                    const int64_t r = block_rel(bk, bv, b, o0, i - 1, blk);
+                    vi.a_ptr = bk.abuf[blk & 1] + r;
+                }
+            }
+            vi.b_ptr = beta_slot(tp, bk, bv, b, o0, i);
             vi.prev_label = t > 1 ? bv.tokens[i - 1] : -1;
             vi.live = 1;
         }
@@ -727,7 +795,7 @@ __device__ __forceinline__ void fetch_visit(const DevLayout &fl, const TapeView 
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) x.key[u] = -1;
     if (!vi.live) return;
-    const float *tb = tp.beta + vi.b_off;
+    const float *tb = vi.b_ptr;
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
         const int j = tid + u * NT;
@@ -741,7 +809,7 @@ __device__ __forceinline__ void fetch_visit(const DevLayout &fl, const TapeView 
         return;
     }
     const LabelInfo lp = fl.label[vi.prev_label];
-    const float *ta = tp.alpha + vi.a_off;
+    const float *ta = vi.a_ptr;
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
         const int j = tid + u * NT;
@@ -756,6 +824,7 @@ template <int NT, int CH>
 __global__ void __launch_bounds__(NT)
 counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv, TapeView tp,
               const CountItem *__restrict__ items, const int32_t *__restrict__ n_items,
+              const int32_t *__restrict__ item_list, const int32_t *__restrict__ list_off, int32_t blk,
               int32_t *__restrict__ item_queue, const VisitInfo *__restrict__ vinfo,
               float *__restrict__ grad, float *__restrict__ partial, int32_t *__restrict__ item_slot,
               int32_t *__restrict__ slot_counter, CountCaps caps)
@@ -779,7 +848,16 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
         den0[q] = CEnt{WFST_NINF, -1};
         den1[q] = CEnt{WFST_NINF, -1};
     }
-    int nit = *n_items;
+    int nit = *n_items, lo = 0;  // items [lo, lo + nit) of the list (or of all items)
+    if (item_list) {
+        lo = list_off[blk];
+        int hi = list_off[blk + 1];
+        if (lo < 0 || hi < lo || hi > nit) {
+            if (blockIdx.x == 0 && tid == 0) atomicOr(bv.health, H_ITEM);
+            lo = hi = 0;
+        }
+        nit = hi - lo;
+    }
     if (nit < 0 || nit > caps.items_cap) {
         if (blockIdx.x == 0 && tid == 0) atomicOr(bv.health, H_ITEM);
         nit = 0;
@@ -787,12 +865,17 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
     for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(item_queue, 1);
         __syncthreads();
-        const int it = s_item;
+        const int idx = s_item;
         __syncthreads();
-        if (it >= nit) break;
-        if (it < 0 || pops > nit) {
+        if (idx >= nit) break;
+        if (idx < 0 || pops > nit) {
             if (tid == 0) atomicOr(bv.health, H_QUEUE);
             break;
+        }
+        const int it = item_list ? item_list[lo + idx] : idx;
+        if (it < 0 || it >= caps.items_cap) {
+            if (tid == 0) atomicOr(bv.health, H_ITEM);
+            continue;
         }
         const CountItem ci = items[it];
         if (ci.first < 0 || ci.last < ci.first || (int64_t)ci.last > bv.N || ci.last - ci.first > caps.V ||
@@ -827,6 +910,24 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
             float acc[MAXR];
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) acc[r] = 0.0f;
+            if (ci.carry && !ci.split) {  // continue the label's sums from the blocks already done
+#pragma unroll
+                for (int k = 0; k < KPP; ++k) {
+                    const int s = (pass * KPP + k) * NW + wave;
+                    if (s < li.n_slices) {
+                        const SliceInfo si = rl.slice[li.slice_first + s];
+                        if (lane < si.width) {
+#pragma unroll
+                            for (int r = 0; r < CH; ++r) {
+                                if (r < si.height) {
+                                    const int arc = rl.elem_arc[si.base + r * si.width + lane];
+                                    if (arc >= 0) acc[k * CH + r] = grad[arc];
+                                }
+                            }
+                        }
+                    }
+                }
+            }
             int src[KPP];  // source state of this lane's chunk in each slice of the pass (-1: none)
 #pragma unroll
             for (int k = 0; k < KPP; ++k) {
@@ -855,11 +956,11 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
                     }
                     // rare: more entries than NT * kPrefetch
                     for (int j = tid + kPrefetch * NT; j < lf.n_segs; j += NT)
-                        bd[j] = (tp.beta[vi.b_off + j] - vi.bm) + vi.o;
+                        bd[j] = (vi.b_ptr[j] - vi.bm) + vi.o;
                     if (vi.prev_label >= 0) {
                         const LabelInfo lp = fl.label[vi.prev_label];
                         for (int j = tid + kPrefetch * NT; j < lp.n_segs; j += NT)
-                            den[fl.seg_key[lp.seg_first + j]] = CEnt{tp.alpha[vi.a_off + j] - vi.cm, v};
+                            den[fl.seg_key[lp.seg_first + j]] = CEnt{vi.a_ptr[j] - vi.cm, v};
                     }
                 }
                 const VisitInfo cur = vi;
@@ -919,29 +1020,35 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
     }
 }
 
+// Sums the partial counts of groups (label, block) whose visits span several
+// work items: one thread per (group, element), partials added in item order,
+// starting from the gradient when the label's sums carry over from earlier
+// blocks.
 template <int NT>
 __global__ void __launch_bounds__(NT)
-counts_fixup(DevLayout fl, const int32_t *__restrict__ item_base, const int32_t *__restrict__ n_items_label,
-             const int64_t *__restrict__ se_off, const int64_t *__restrict__ se_total,
-             const int32_t *__restrict__ item_slot, const float *__restrict__ partial,
-             float *__restrict__ grad, CountCaps caps, int32_t M, uint32_t *health)
+counts_fixup(DevLayout rl, const CountItem *__restrict__ items, const int32_t *__restrict__ item_base,
+             const int32_t *__restrict__ n_items_key, const int64_t *__restrict__ se_off,
+             const int64_t *__restrict__ se_total, const int32_t *__restrict__ item_slot,
+             const float *__restrict__ partial, float *__restrict__ grad, CountCaps caps, int32_t MK, int32_t K,
+             uint32_t *health)
 {
     const int64_t W = *se_total;
     for (int64_t w = blockIdx.x * (int64_t)NT + threadIdx.x; w < W; w += (int64_t)gridDim.x * NT) {
-        int lo = 0, hi = M;  // last label with se_off <= w
+        int lo = 0, hi = MK;  // last group with se_off <= w
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (se_off[mid] <= w) lo = mid; else hi = mid;
         }
-        const int a = lo;
-        const LabelInfo li = fl.label[a];
-        const int64_t e = w - se_off[a];
-        const int first = item_base[a], k = n_items_label[a];
+        const int key = lo;
+        const LabelInfo li = rl.label[key / K];
+        const int64_t e = w - se_off[key];
+        const int first = item_base[key], k = n_items_key[key];
         if (e >= li.n_elems || k < 2 || first < 0 || first + k > caps.items_cap) {
             atomicOr(health, H_ITEM);
             continue;
         }
-        float s = 0.0f;
+        const int arc = rl.elem_arc[li.elem_first + e];
+        float s = (items[first].carry && arc >= 0) ? grad[arc] : 0.0f;
         bool ok = true;
         int x = 0;
         for (; x + 4 <= k; x += 4) {
@@ -953,21 +1060,31 @@ counts_fixup(DevLayout fl, const int32_t *__restrict__ item_base, const int32_t 
                 ok = ok && sl[u] >= 0 && sl[u] < caps.slot_cap;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = ok ? partial[(int64_t)sl[u] * fl.max_elems + e] : 0.0f;
+            for (int u = 0; u < 4; ++u) v[u] = ok ? partial[(int64_t)sl[u] * rl.max_elems + e] : 0.0f;
 #pragma unroll
             for (int u = 0; u < 4; ++u) s += v[u];
         }
         for (; x < k; ++x) {
             const int sl = item_slot[first + x];
             ok = ok && sl >= 0 && sl < caps.slot_cap;
-            if (ok) s += partial[(int64_t)sl * fl.max_elems + e];
+            if (ok) s += partial[(int64_t)sl * rl.max_elems + e];
         }
         if (!ok) {
             atomicOr(health, H_SLOT);
             continue;
         }
-        const int arc = fl.elem_arc[li.elem_first + e];
         if (arc >= 0) grad[arc] = s;
+    }
+}
+
+// element count of every group (label, block) of block blk (all blocks when
+// blk < 0) whose visits span several count work items
+__global__ void split_group_elems(const LabelInfo *__restrict__ label, const int32_t *__restrict__ n_items_key,
+                                  int32_t MK, int32_t K, int32_t blk, int32_t *__restrict__ out)
+{
+    for (int key = blockIdx.x * blockDim.x + threadIdx.x; key < MK; key += gridDim.x * blockDim.x) {
+        const bool mine = blk < 0 || K - 1 - key % K == blk;
+        out[key] = (mine && n_items_key[key] > 1) ? label[key / K].n_elems : 0;
     }
 }
 
@@ -1006,7 +1123,7 @@ __global__ void final_rows(BatchView bv, TapeView tp, DevLayout fl, int32_t Q, i
             continue;
         }
         const LabelInfo lf = fl.label[a];
-        const float *ta = tp.alpha + bv.tok_off[i];
+        const float *ta = tp.alpha + (tp.ck_off ? tp.ck_off[i] : bv.tok_off[i]);
         const float c = tp.a_max[i];
         const float o = (float)(tp.a_log[i] - tp.log_z[b]);
         for (int j = lane; j < lf.n_segs; j += 64) {
@@ -1044,17 +1161,60 @@ __global__ void sum_groups(const float *__restrict__ S, int32_t ng, int32_t Q, i
     }
 }
 
-// element count of every label whose visits span several count work items
-__global__ void split_label_elems(const LabelInfo *__restrict__ label, const int32_t *__restrict__ n_items_label,
-                                  int32_t M, int32_t *__restrict__ out)
+// ---- checkpoint planning -------------------------------------------------
+
+// longest sentence of the batch (one workgroup)
+__global__ void __launch_bounds__(1024) batch_max_len(const int32_t *__restrict__ offsets, int32_t B,
+                                                      int32_t *__restrict__ out)
 {
-    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < M; a += gridDim.x * blockDim.x)
-        out[a] = n_items_label[a] > 1 ? label[a].n_elems : 0;
+    __shared__ int32_t m;
+    if (threadIdx.x == 0) m = 0;
+    __syncthreads();
+    int32_t x = 0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) x = max(x, offsets[b + 1] - offsets[b]);
+    atomicMax(&m, x);
+    __syncthreads();
+    if (threadIdx.x == 0) *out = m;
 }
 
-// =====================================================================
-// Small helpers
-// =====================================================================
+// per token: size of its kept alpha~ (steps divisible by c and the last step)
+__global__ void ckpt_sizes(const int32_t *__restrict__ offsets, int32_t B, const int32_t *__restrict__ tokens,
+                           const LabelInfo *__restrict__ label, int32_t M, int32_t c, int64_t *__restrict__ size)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        const int o0 = offsets[b], T = offsets[b + 1] - o0;
+        for (int t = 1; t <= T; ++t) {
+            const int a = tokens[o0 + t - 1];
+            const bool keep = (t % c == 0 || t == T) && a >= 0 && a < M;
+            size[o0 + t - 1] = keep ? label[a].n_segs : 0;
+        }
+    }
+}
+
+// ck_off[i] = -1 for tokens whose alpha~ is not kept
+__global__ void ckpt_mark(const int64_t *__restrict__ size, int64_t N, int64_t *__restrict__ ck_off)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        if (size[i] == 0) ck_off[i] = -1;
+}
+
+// per sentence: the largest block of c steps, in compact tape entries
+__global__ void block_sizes(const int32_t *__restrict__ offsets, int32_t B, const int32_t *__restrict__ tokens,
+                            const LabelInfo *__restrict__ label, int32_t M, const int64_t *__restrict__ tok_off,
+                            int32_t c, int64_t *__restrict__ out)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        const int o0 = offsets[b], T = offsets[b + 1] - o0;
+        int64_t m = 0;
+        for (int t0 = 0; t0 < T; t0 += c) {
+            const int t1 = min(T, t0 + c);
+            const int a = tokens[o0 + t1 - 1];
+            const int64_t end = tok_off[o0 + t1 - 1] + ((a >= 0 && a < M) ? label[a].n_segs : 0);
+            m = max(m, end - tok_off[o0 + t0]);
+        }
+        out[b] = m;
+    }
+}
 
 __global__ void fill_f32(float *__restrict__ p, int64_t n, float v)
 {
@@ -1090,10 +1250,12 @@ __global__ void token_segments(const int32_t *__restrict__ tokens, int64_t N, co
     }
 }
 
-// token -> sentence, and visit keys (label) for grouping
+// token -> sentence, and visit keys for grouping: the label, refined by the
+// checkpoint block (later blocks first) when c > 0: key = label * K + (K-1-block)
 __global__ void token_owner(const int32_t *__restrict__ offsets, int32_t B, int64_t N,
                             const int32_t *__restrict__ tokens, int32_t *__restrict__ tok_sent,
-                            int32_t *__restrict__ vis_key, int32_t *__restrict__ vis_idx, int32_t M)
+                            int32_t *__restrict__ vis_key, int32_t *__restrict__ vis_idx, int32_t M, int32_t c,
+                            int32_t K)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
         int lo = 0, hi = B;  // last b with offsets[b] <= i
@@ -1103,7 +1265,9 @@ __global__ void token_owner(const int32_t *__restrict__ offsets, int32_t B, int6
         }
         tok_sent[i] = lo;
         const int a = tokens[i];
-        vis_key[i] = (a >= 0 && a < M) ? a : M;  // invalid tokens sort last
+        int key = (a >= 0 && a < M) ? a * K : M * K;  // invalid tokens sort last
+        if (c > 0 && key < M * K) key += K - 1 - min(K - 1, (int)(i - offsets[lo]) / c);
+        vis_key[i] = key;
         vis_idx[i] = (int)i;
     }
 }
@@ -1131,25 +1295,66 @@ __global__ void label_groups(const int32_t *__restrict__ skeys, int64_t N, int32
     }
 }
 
+// items of every key group (key = label * K + K-1-block); a label is split
+// when its items over all blocks number more than one
 __global__ void label_items(const int32_t *__restrict__ grp_lo, const int32_t *__restrict__ grp_n,
-                            const int32_t *__restrict__ n_items_per_label,
-                            const int32_t *__restrict__ item_base, int32_t M, int32_t V,
+                            const int32_t *__restrict__ n_items_per_key, const int32_t *__restrict__ item_base,
+                            int32_t MK, int32_t K, int32_t V,
                             CountItem *__restrict__ items, int32_t *__restrict__ n_items, int32_t items_cap,
                             uint32_t *__restrict__ health)
 {
-    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < M; a += gridDim.x * blockDim.x) {
-        const int k = n_items_per_label[a];
-        const int base = item_base[a];
+    for (int key = blockIdx.x * blockDim.x + threadIdx.x; key < MK; key += gridDim.x * blockDim.x) {
+        const int k = n_items_per_key[key];
+        const int base = item_base[key];
         if (base < 0 || k < 0 || base + k > items_cap) {
             atomicOr(health, H_GROUP);
             continue;
         }
+        const int a = key / K;
+        const int split = k > 1 ? 1 : 0;
+        int carry = 0;  // keys of a label are processed in increasing order (later blocks first)
+        for (int r = a * K; r < key; ++r) carry |= n_items_per_key[r] > 0;
         for (int x = 0; x < k; ++x) {
-            const int f = grp_lo[a] + x * V;
-            const int l = min(grp_lo[a] + grp_n[a], f + V);
-            items[base + x] = CountItem{f, l, a, k > 1 ? 1 : 0};
+            const int f = grp_lo[key] + x * V;
+            const int l = min(grp_lo[key] + grp_n[key], f + V);
+            items[base + x] = CountItem{f, l, a, split, K - 1 - key % K, carry};
         }
-        if (a == M - 1) *n_items = base + k;
+        if (key == MK - 1) *n_items = base + k;
+    }
+}
+
+// Item indices listed per checkpoint block (one workgroup): list_off[K+1]
+// offsets, list[] indices.  The order inside a block does not affect results.
+__global__ void __launch_bounds__(1024) items_by_block(const CountItem *__restrict__ items,
+                                                       const int32_t *__restrict__ n_items, int32_t K,
+                                                       int32_t items_cap, int32_t *__restrict__ list,
+                                                       int32_t *__restrict__ list_off, uint32_t *__restrict__ health)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *cnt = reinterpret_cast<int32_t *>(smem);  // [K] counts, then [K] cursors
+    int32_t *cur = cnt + K;
+    const int n = min(max(*n_items, 0), items_cap);
+    for (int k = threadIdx.x; k < K; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    for (int it = threadIdx.x; it < n; it += blockDim.x) {
+        const int k = items[it].block;
+        if (k >= 0 && k < K) atomicAdd(&cnt[k], 1);
+        else atomicOr(health, H_ITEM);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < K; ++k) {
+            list_off[k] = run;
+            cur[k] = run;
+            run += cnt[k];
+        }
+        list_off[K] = run;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < n; it += blockDim.x) {
+        const int k = items[it].block;
+        if (k >= 0 && k < K) list[atomicAdd(&cur[k], 1)] = it;
     }
 }
 

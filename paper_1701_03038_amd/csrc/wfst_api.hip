@@ -90,7 +90,8 @@ int ensure_t(Buf &b, int64_t count, hipStream_t s, T **out)
 enum WsSlot {
     W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
-    W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_NUM
+    W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
+    W_ILIST, W_ILOFF, W_NUM
 };
 
 // small device counters kept together (one allocation)
@@ -98,7 +99,7 @@ enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_ITEMQ = 3, C_TOTAL = 4 
                C_SETOTAL = 6 /* int64 at byte 24 */, C_COUNT = 8 };
 
 struct TapeBufs {
-    Buf order, tok_off, alpha, a_max, a_log, log_z, tiles, total;
+    Buf order, tok_off, alpha, a_max, a_log, log_z, tiles, total, ck_size, ck_off, blk_size, blk_base;
 };
 
 }  // namespace
@@ -106,6 +107,8 @@ struct TapeBufs {
 struct wfst_fst {
     int device = 0;
     int32_t Q = 0, M = 0, start = 0, chunk = 16, nt = 256;
+    int32_t ckpt_mode = 0;                        // wfst_options.checkpoint
+    int64_t tape_budget = (int64_t)8 << 30;       // bytes of alpha + beta tape before auto checkpointing
     int64_t A = 0;
     DevLayout fwd, rev;
     float *final_score = nullptr;
@@ -139,6 +142,11 @@ struct wfst_tape {
     int64_t *tok_off = nullptr;
     float *alpha = nullptr, *a_max = nullptr;
     double *a_log = nullptr, *log_z = nullptr;
+    // checkpointed tape (ck_c > 0): alpha~ kept every ck_c steps and at the last step
+    int32_t ck_c = 0, ck_K = 1;
+    int64_t *ck_off = nullptr;    // [N] offset of a kept token's alpha~, -1 otherwise
+    int64_t *blk_base = nullptr;  // [B] start of each sentence in a block buffer
+    int64_t blk_total = 0;        // floats of one block buffer
 };
 
 namespace {
@@ -322,6 +330,78 @@ int make_plan(const wfst_fst *f, hipStream_t s, int32_t B, int64_t N, const int3
 
 constexpr int64_t kBoundCapBytes = (int64_t)2 << 30;
 
+TapeView tape_view(const wfst_tape *t)
+{
+    TapeView tp;
+    tp.alpha = t->alpha;
+    tp.a_max = t->a_max;
+    tp.a_log = t->a_log;
+    tp.log_z = t->log_z;
+    tp.ck_off = t->ck_c > 0 ? t->ck_off : nullptr;
+    return tp;
+}
+
+// Decide whether the forward tape keeps every alpha~ or only checkpoints
+// (every c = ceil(sqrt(T_max)) steps and the last step), and lay out the
+// checkpointed tape and the per-sentence block buffers.  *alpha_elems gets the
+// tape size.  Auto mode checkpoints when alpha + beta tapes would exceed the
+// FST's budget; deciding then needs the exact sizes from the device.
+int plan_checkpoints(wfst_fst *f, hipStream_t s, wfst_tape *t, int64_t *tiles, int64_t *dev_total,
+                     const Plan &p, int64_t *alpha_elems)
+{
+    const int32_t B = t->B;
+    const int64_t N = t->N;
+    t->ck_c = 0;
+    t->ck_K = 1;
+    if (f->ckpt_mode == 2 || N == 0) return WFST_OK;
+    const int64_t bytes_bound = 2 * (int64_t)sizeof(float) * p.total;
+    if (f->ckpt_mode != 1 && bytes_bound <= f->tape_budget) return WFST_OK;
+    // exact tape size and longest sentence
+    int32_t *dev_tmax = reinterpret_cast<int32_t *>(dev_total + 1);
+    hipLaunchKernelGGL(batch_max_len, dim3(1), dim3(1024), 0, s, t->offsets, B, dev_tmax);
+    int64_t host[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(host, dev_total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const int64_t total = host[0];
+    int32_t tmax;
+    std::memcpy(&tmax, &host[1], sizeof(int32_t));
+    if (f->ckpt_mode != 1 && 2 * (int64_t)sizeof(float) * total <= f->tape_budget) {
+        t->total = total;
+        return WFST_OK;
+    }
+    if (tmax <= 0) return WFST_OK;
+    int32_t c = 1;
+    while ((int64_t)c * c < tmax) ++c;
+    t->ck_c = c;
+    t->ck_K = (tmax + c - 1) / c;
+    if ((int64_t)f->M * t->ck_K >= INT32_MAX)
+        return set_err(WFST_EUNSUPPORTED, "labels x checkpoint blocks exceed 2^31");
+    TapeBufs *tb = t->bufs;
+    int64_t *size, *bsize;
+    TRY(ensure_t(tb->ck_size, N, s, &size));
+    TRY(ensure_t(tb->ck_off, N, s, &t->ck_off));
+    TRY(ensure_t(tb->blk_size, B, s, &bsize));
+    TRY(ensure_t(tb->blk_base, B, s, &t->blk_base));
+    hipLaunchKernelGGL(ckpt_sizes, dim3(grid_for(B, 256)), dim3(256), 0, s, t->offsets, B, t->tokens,
+                       (const LabelInfo *)f->fwd.label, f->M, c, size);
+    ScanSource src;
+    src.i64 = size;
+    TRY(launch_scan<int64_t>(s, src, N, tiles, t->ck_off, dev_total));
+    hipLaunchKernelGGL(ckpt_mark, dim3(grid_for(N, 256, 8192)), dim3(256), 0, s, (const int64_t *)size, N,
+                       t->ck_off);
+    hipLaunchKernelGGL(block_sizes, dim3(grid_for(B, 256)), dim3(256), 0, s, t->offsets, B, t->tokens,
+                       (const LabelInfo *)f->fwd.label, f->M, (const int64_t *)t->tok_off, c, bsize);
+    ScanSource bsrc;
+    bsrc.i64 = bsize;
+    TRY(launch_scan<int64_t>(s, bsrc, B, tiles, t->blk_base, dev_total + 1));
+    HIP_OK(hipMemcpyAsync(host, dev_total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    *alpha_elems = host[0];
+    t->blk_total = host[1];
+    t->total = total;
+    return WFST_OK;
+}
+
 template <int NT>
 int launch_viterbi(const wfst_fst *f, hipStream_t s, const BatchView &bv, int2 *bp, int32_t *path_tmp,
                    float *best_score, int32_t *best_arcs, int32_t *best_olabels)
@@ -338,65 +418,83 @@ int launch_viterbi(const wfst_fst *f, hipStream_t s, const BatchView &bv, int2 *
 }
 
 template <int NT>
-int launch_forward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, float *log_z)
+int launch_forward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
+                   float *log_z)
 {
     const size_t lds = lds_lse(f, f->fwd);
     int grid = 0;
     TRY(persistent_grid(f, forward_sweep<NT>, NT, lds, bv.B, &grid));
     ProfScope prof(f, s, WFST_KERNEL_FORWARD);
     hipLaunchKernelGGL((forward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start,
-                       (const float *)f->final_score, bv, tp, log_z);
+                       (const float *)f->final_score, bv, tp, bk, log_z);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 
 template <int NT>
-int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp)
+int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk)
 {
     const size_t lds = lds_lse(f, f->rev);
     int grid = 0;
     TRY(persistent_grid(f, backward_sweep<NT>, NT, lds, bv.B, &grid));
     ProfScope prof(f, s, WFST_KERNEL_BACKWARD);
     hipLaunchKernelGGL((backward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start,
-                       (const float *)f->final_score, (const float *)f->final_max, bv, tp);
+                       (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 
+// Arguments of the count kernel that stay the same over its launches.
+struct CountLaunch {
+    const CountItem *items;
+    const int32_t *n_items;
+    const int32_t *list, *list_off;  // per-block item lists (checkpointing), else null
+    int32_t *item_queue;
+    int64_t items_bound;
+    const VisitInfo *vinfo;
+    float *grad, *partial;
+    int32_t *item_slot, *slot_counter;
+    CountCaps caps;
+};
+
 template <int NT, int CH>
 int launch_counts_nt(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
-                     const CountItem *items, const int32_t *n_items, int32_t *item_queue, int64_t items_bound,
-                     const VisitInfo *vinfo, float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter,
-                     CountCaps caps)
+                     const CountLaunch &c, int32_t blk)
 {
     const size_t lds = lds_counts(f);
     int grid = 0;
-    TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, items_bound, &grid));
+    TRY(persistent_grid(f, counts_kernel<NT, CH>, NT, lds, c.items_bound, &grid));
     ProfScope prof(f, s, WFST_KERNEL_COUNTS);
     hipLaunchKernelGGL((counts_kernel<NT, CH>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start, bv,
-                       tp, items, n_items, item_queue, vinfo, grad, partial, item_slot, slot_counter, caps);
+                       tp, c.items, c.n_items, c.list, c.list_off, blk, c.item_queue, c.vinfo, c.grad, c.partial,
+                       c.item_slot, c.slot_counter, c.caps);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 
 // Workgroup size of the count kernel: enough wavefronts for the widest label
-// of the reverse layout to fit one pass (KPP = 64 / CH slices per wavefront).
+// of the reverse layout to fit one pass (KPP slices per wavefront).
 template <int CH>
 int launch_counts_ch(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp,
-                     const CountItem *items, const int32_t *n_items, int32_t *item_queue, int64_t items_bound,
-                     const VisitInfo *vinfo, float *grad, float *partial, int32_t *item_slot, int32_t *slot_counter,
-                     CountCaps caps)
+                     const CountLaunch &c, int32_t blk)
 {
     constexpr int KPP = count_slices_per_wave(CH);
     const int waves = (f->rev.max_slices + KPP - 1) / KPP;
-    if (waves > 8)
-        return launch_counts_nt<1024, CH>(f, s, bv, tp, items, n_items, item_queue, items_bound, vinfo, grad, partial,
-                                          item_slot, slot_counter, caps);
-    if (waves > 4)
-        return launch_counts_nt<512, CH>(f, s, bv, tp, items, n_items, item_queue, items_bound, vinfo, grad, partial,
-                                         item_slot, slot_counter, caps);
-    return launch_counts_nt<256, CH>(f, s, bv, tp, items, n_items, item_queue, items_bound, vinfo, grad, partial, item_slot,
-                                     slot_counter, caps);
+    if (waves > 8) return launch_counts_nt<1024, CH>(f, s, bv, tp, c, blk);
+    if (waves > 4) return launch_counts_nt<512, CH>(f, s, bv, tp, c, blk);
+    return launch_counts_nt<256, CH>(f, s, bv, tp, c, blk);
+}
+
+// CH = slice height bound of the reverse layout
+int launch_counts(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const CountLaunch &c,
+                  int32_t blk)
+{
+    const int ch = f->rev.max_height;
+    if (ch <= 4) return launch_counts_ch<4>(f, s, bv, tp, c, blk);
+    if (ch <= 8) return launch_counts_ch<8>(f, s, bv, tp, c, blk);
+    if (ch <= 16) return launch_counts_ch<16>(f, s, bv, tp, c, blk);
+    if (ch <= 32) return launch_counts_ch<32>(f, s, bv, tp, c, blk);
+    return launch_counts_ch<64>(f, s, bv, tp, c, blk);
 }
 
 #define DISPATCH_NT(rc, nt, fn, ...)                  \
@@ -428,7 +526,7 @@ BatchView make_view(const wfst_fst *f, int32_t B, int64_t N, const int32_t *offs
 // Stable sort of token positions by label: visits[] lists positions grouped by
 // label, in increasing position inside each label; skeys[] their labels.
 int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, const int32_t *offsets, int32_t B,
-                int32_t **visits_out, int32_t **skeys_out, int32_t *tok_sent)
+                int32_t c, int32_t K, int32_t **visits_out, int32_t **skeys_out, int32_t *tok_sent)
 {
     int32_t *k0, *k1, *v0, *v1;
     TRY(ensure_t(f->ws[W_KEY0], N, s, &k0));
@@ -436,9 +534,9 @@ int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, co
     TRY(ensure_t(f->ws[W_VAL0], N, s, &v0));
     TRY(ensure_t(f->ws[W_VAL1], N, s, &v1));
     hipLaunchKernelGGL(token_owner, dim3(grid_for(N, 256)), dim3(256), 0, s, offsets, B, N, tokens, tok_sent, k0,
-                       v0, f->M);
-    int bits = 1;
-    while (bits < 31 && ((int64_t)1 << bits) <= (int64_t)f->M) ++bits;
+                       v0, f->M, c, K);
+    int bits = 1;  // keys are < M * K + 1
+    while (bits < 31 && ((int64_t)1 << bits) <= (int64_t)f->M * K) ++bits;
     const int passes = (bits + 7) / 8;
     const int64_t ntiles = (N + kSortTile - 1) / kSortTile;
     int64_t *hist, *tiles;
@@ -479,11 +577,7 @@ int final_posteriors(wfst_fst *f, const wfst_tape *tape, const float *grad_log_z
     float *rows, *S;
     TRY(ensure_t(f->ws[W_FROWS], nb_max * Q, s, &rows));
     TRY(ensure_t(f->ws[W_FSUM], (nb_max + G - 1) / G * Q, s, &S));
-    TapeView tp;
-    tp.alpha = tape->alpha;
-    tp.a_max = tape->a_max;
-    tp.a_log = tape->a_log;
-    tp.log_z = tape->log_z;
+    const TapeView tp = tape_view(tape);
     const BatchView bv = make_view(f, B, tape->N, tape->offsets, tape->tokens, tape->order, tape->tok_off, nullptr,
                                    tape->status);
     for (int64_t b0 = 0; b0 < B; b0 += nb_max) {
@@ -597,6 +691,8 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         int nt = opt.threads_per_sentence > 0 ? opt.threads_per_sentence : 256;
         if (nt != 64 && nt != 128 && nt != 256 && nt != 512 && nt != 1024)
             return set_err(WFST_EINVAL, "threads_per_sentence must be 64, 128, 256, 512 or 1024");
+        if (opt.checkpoint < -1 || opt.checkpoint > 2) return set_err(WFST_EINVAL, "checkpoint must be -1, 0, 1 or 2");
+        if (opt.tape_budget_bytes < 0) return set_err(WFST_EINVAL, "tape_budget_bytes must be >= 0");
 
         hipStream_t s = as_stream(stream);
         wfst_fst *f = new wfst_fst();
@@ -606,6 +702,8 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         f->A = num_arcs;
         f->chunk = L;
         f->nt = nt;
+        f->ckpt_mode = opt.checkpoint;
+        if (opt.tape_budget_bytes > 0) f->tape_budget = opt.tape_budget_bytes;
         if (hipGetDevice(&f->device) != hipSuccess) {
             delete f;
             return set_err(WFST_EHIP, "hipGetDevice failed");
@@ -828,17 +926,19 @@ int wfst_forward(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const in
         int64_t *tiles, *dev_total;
         rc = ensure_t(tb->order, batch, s, &t->order);
         if (rc == WFST_OK) rc = ensure_t(tb->tok_off, N, s, &t->tok_off);
-        if (rc == WFST_OK) rc = ensure_t(tb->tiles, scan_tiles_for(N), s, &tiles);
-        if (rc == WFST_OK) rc = ensure_t(tb->total, 1, s, &dev_total);
+        if (rc == WFST_OK) rc = ensure_t(tb->tiles, scan_tiles_for(std::max<int64_t>(N, batch)), s, &tiles);
+        if (rc == WFST_OK) rc = ensure_t(tb->total, 2, s, &dev_total);
         if (rc == WFST_OK) rc = ensure_t(f->ws[W_COUNTERS], C_COUNT, s, &counters);
         Plan p;
         if (rc == WFST_OK)
             rc = make_plan(f, s, batch, N, offsets, tokens, t->order, t->tok_off, tiles, dev_total,
                            kBoundCapBytes / 4, p);
+        int64_t alpha_elems = p.total;
         if (rc == WFST_OK) {
             t->total = p.total;
-            rc = ensure_t(tb->alpha, p.total, s, &t->alpha);
+            rc = plan_checkpoints(f, s, t, tiles, dev_total, p, &alpha_elems);
         }
+        if (rc == WFST_OK) rc = ensure_t(tb->alpha, std::max<int64_t>(alpha_elems, 1), s, &t->alpha);
         if (rc == WFST_OK) rc = ensure_t(tb->a_max, N, s, &t->a_max);
         if (rc == WFST_OK) rc = ensure_t(tb->a_log, N, s, &t->a_log);
         if (rc == WFST_OK) rc = ensure_t(tb->log_z, batch, s, &t->log_z);
@@ -846,12 +946,8 @@ int wfst_forward(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const in
             hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
             const BatchView bv =
                 make_view(f, batch, N, offsets, tokens, t->order, t->tok_off, counters + C_QUEUE, status);
-            TapeView tp;
-            tp.alpha = t->alpha;
-            tp.a_max = t->a_max;
-            tp.a_log = t->a_log;
-            tp.log_z = t->log_z;
-            DISPATCH_NT(rc, f->nt, launch_forward, f, s, bv, tp, log_z)
+            const TapeView tp = tape_view(t);
+            DISPATCH_NT(rc, f->nt, launch_forward, f, s, bv, tp, BlockView(), log_z)
         }
     }
     if (rc != WFST_OK) {
@@ -888,13 +984,21 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
         HIP_OK(hipGetLastError());
         return WFST_OK;
     }
-    TapeView tp;
-    tp.alpha = tape->alpha;
-    tp.a_max = tape->a_max;
-    tp.a_log = tape->a_log;
-    tp.log_z = tape->log_z;
+    TapeView tp = tape_view(tape);
+    const int32_t K = tape->ck_c > 0 ? tape->ck_K : 1;
+    BlockView bk;  // c = 0: the whole tape is resident
     int32_t *counters;
-    TRY(ensure_t(f->ws[W_BETA], tape->total, s, &tp.beta));
+    if (tape->ck_c > 0) {
+        bk.c = tape->ck_c;
+        bk.base = tape->blk_base;
+        const int64_t nb = std::max<int64_t>(tape->blk_total, 1);
+        TRY(ensure_t(f->ws[W_ABUF0], nb, s, &bk.abuf[0]));
+        TRY(ensure_t(f->ws[W_ABUF1], nb, s, &bk.abuf[1]));
+        TRY(ensure_t(f->ws[W_BBUF0], nb, s, &bk.bbuf[0]));
+        TRY(ensure_t(f->ws[W_BBUF1], nb, s, &bk.bbuf[1]));
+    } else {
+        TRY(ensure_t(f->ws[W_BETA], tape->total, s, &tp.beta));
+    }
     TRY(ensure_t(f->ws[W_BMAX], N, s, &tp.b_max));
     TRY(ensure_t(f->ws[W_BLOG], N, s, &tp.b_log));
     TRY(ensure_t(f->ws[W_LZB], B, s, &tp.log_z_bwd));
@@ -903,19 +1007,22 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     const BatchView bv = make_view(f, B, N, tape->offsets, tape->tokens, tape->order, tape->tok_off,
                                    counters + C_QUEUE, tape->status);
     int rc;
-    DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp)
-    if (rc != WFST_OK) return rc;
+    if (bk.c == 0) {
+        DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk)
+        if (rc != WFST_OK) return rc;
+    }
 
-    // group the visits (token positions) by input label, stable in position
+    // group the visits (token positions) by (input label, checkpoint block), stable in position
     const int32_t V = 64;
+    const int32_t MK = f->M * K;
     int32_t *tok_sent, *visits, *skeys, *grp_lo, *grp_n, *nip, *item_base, *item_slot;
     TRY(ensure_t(f->ws[W_TOKSENT], N, s, &tok_sent));
-    TRY(sort_visits(f, s, N, tape->tokens, tape->offsets, B, &visits, &skeys, tok_sent));
-    TRY(ensure_t(f->ws[W_GRPLO], f->M, s, &grp_lo));
-    TRY(ensure_t(f->ws[W_GRPN], f->M, s, &grp_n));
-    TRY(ensure_t(f->ws[W_NIP], f->M, s, &nip));
-    TRY(ensure_t(f->ws[W_ITEMBASE], f->M, s, &item_base));
-    const int64_t items_bound = N / V + std::min<int64_t>(f->M, N) + 1;
+    TRY(sort_visits(f, s, N, tape->tokens, tape->offsets, B, tape->ck_c, K, &visits, &skeys, tok_sent));
+    TRY(ensure_t(f->ws[W_GRPLO], MK, s, &grp_lo));
+    TRY(ensure_t(f->ws[W_GRPN], MK, s, &grp_n));
+    TRY(ensure_t(f->ws[W_NIP], MK, s, &nip));
+    TRY(ensure_t(f->ws[W_ITEMBASE], MK, s, &item_base));
+    const int64_t items_bound = N / V + std::min<int64_t>(MK, N) + 1;
     CountItem *items;
     TRY(ensure_t(f->ws[W_ITEMS], items_bound, s, &items));
     TRY(ensure_t(f->ws[W_ITEMSLOT], items_bound, s, &item_slot));
@@ -923,57 +1030,76 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     float *partial;
     TRY(ensure_t(f->ws[W_PARTIAL], split_bound * (int64_t)std::max(f->rev.max_elems, 1), s, &partial));
     int64_t *tiles;
-    TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(std::max<int64_t>(f->M, 256 * ((N + kSortTile - 1) / kSortTile))),
+    TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(std::max<int64_t>(MK, 256 * ((N + kSortTile - 1) / kSortTile))),
                  s, &tiles));
-    hipLaunchKernelGGL(label_groups, dim3(grid_for(f->M, 256)), dim3(256), 0, s, (const int32_t *)skeys, N, f->M, V,
+    hipLaunchKernelGGL(label_groups, dim3(grid_for(MK, 256)), dim3(256), 0, s, (const int32_t *)skeys, N, MK, V,
                        grp_lo, grp_n, nip);
     ScanSource src;
     src.i32 = nip;
-    TRY(launch_scan<int32_t>(s, src, f->M, tiles, item_base, nullptr));
-    hipLaunchKernelGGL(label_items, dim3(grid_for(f->M, 256)), dim3(256), 0, s, (const int32_t *)grp_lo,
-                       (const int32_t *)grp_n, (const int32_t *)nip, (const int32_t *)item_base, f->M, V, items,
+    TRY(launch_scan<int32_t>(s, src, MK, tiles, item_base, nullptr));
+    hipLaunchKernelGGL(label_items, dim3(grid_for(MK, 256)), dim3(256), 0, s, (const int32_t *)grp_lo,
+                       (const int32_t *)grp_n, (const int32_t *)nip, (const int32_t *)item_base, MK, K, V, items,
                        counters + C_NITEMS, (int32_t)items_bound, f->health);
     CountCaps caps;
     caps.items_cap = (int32_t)items_bound;
     caps.slot_cap = (int32_t)split_bound;
     caps.V = V;
+    int32_t *list = nullptr, *list_off = nullptr;
+    if (bk.c > 0) {
+        TRY(ensure_t(f->ws[W_ILIST], items_bound, s, &list));
+        TRY(ensure_t(f->ws[W_ILOFF], K + 1, s, &list_off));
+        hipLaunchKernelGGL(items_by_block, dim3(1), dim3(1024), 2 * K * sizeof(int32_t), s, (const CountItem *)items,
+                           (const int32_t *)(counters + C_NITEMS), K, (int32_t)items_bound, list, list_off,
+                           f->health);
+    }
     VisitInfo *vinfo;
     TRY(ensure_t(f->ws[W_VINFO], N, s, &vinfo));
-    hipLaunchKernelGGL(visit_table, dim3(grid_for(N, 256)), dim3(256), 0, s, bv, tp, (const int32_t *)visits,
-                       (const int32_t *)tok_sent, grad_log_z, vinfo);
-    const int ch = f->rev.max_height;  // slice height bound of the reverse layout
-    if (ch <= 4)
-        rc = launch_counts_ch<4>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
-                                 partial, item_slot, counters + C_SLOTS, caps);
-    else if (ch <= 8)
-        rc = launch_counts_ch<8>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
-                                 partial, item_slot, counters + C_SLOTS, caps);
-    else if (ch <= 16)
-        rc = launch_counts_ch<16>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
-                                  partial, item_slot, counters + C_SLOTS, caps);
-    else if (ch <= 32)
-        rc = launch_counts_ch<32>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
-                                  partial, item_slot, counters + C_SLOTS, caps);
-    else
-        rc = launch_counts_ch<64>(f, s, bv, tp, items, counters + C_NITEMS, counters + C_ITEMQ, items_bound, vinfo, grad_arc_score,
-                                  partial, item_slot, counters + C_SLOTS, caps);
-    if (rc != WFST_OK) return rc;
-    // labels split over several items: one thread per (label, element) sums the partials
+    // per-visit records read the backward normalisers: built after the beta sweep (of each block)
+    auto build_visits = [&]() {
+        hipLaunchKernelGGL(visit_table, dim3(grid_for(N, 256)), dim3(256), 0, s, bv, tp, bk,
+                           (const int32_t *)visits, (const int32_t *)tok_sent, grad_log_z, vinfo);
+    };
     int32_t *split_e;
     int64_t *se_off;
-    TRY(ensure_t(f->ws[W_SPLITE], f->M, s, &split_e));
-    TRY(ensure_t(f->ws[W_SEOFF], f->M, s, &se_off));
-    hipLaunchKernelGGL(split_label_elems, dim3(grid_for(f->M, 256)), dim3(256), 0, s,
-                       (const LabelInfo *)f->rev.label, (const int32_t *)nip, f->M, split_e);
-    ScanSource ssrc;
-    ssrc.i32 = split_e;
+    TRY(ensure_t(f->ws[W_SPLITE], MK, s, &split_e));
+    TRY(ensure_t(f->ws[W_SEOFF], MK, s, &se_off));
     int64_t *se_total = reinterpret_cast<int64_t *>(counters + C_SETOTAL);
-    TRY(launch_scan<int64_t>(s, ssrc, f->M, tiles, se_off, se_total));
-    const int64_t fix_bound = std::min<int64_t>(split_bound, f->M) * (int64_t)std::max(f->rev.max_elems, 1);
-    hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(fix_bound, 256, 16384)), dim3(256), 0, s, f->rev,
-                       (const int32_t *)item_base, (const int32_t *)nip, (const int64_t *)se_off,
-                       (const int64_t *)se_total, (const int32_t *)item_slot, (const float *)partial,
-                       grad_arc_score, caps, f->M, f->health);
+    const CountLaunch cl{items, counters + C_NITEMS, list, list_off, counters + C_ITEMQ, items_bound, vinfo,
+                         grad_arc_score, partial, item_slot, counters + C_SLOTS, caps};
+    // one block of steps (all of them without checkpointing): counts, then the
+    // groups split over several items
+    auto counts_block = [&](int32_t blk) -> int {
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_ITEMQ, (int64_t)1, 0);
+        TRY(launch_counts(f, s, bv, tp, cl, blk));
+        hipLaunchKernelGGL(split_group_elems, dim3(grid_for(MK, 256)), dim3(256), 0, s,
+                           (const LabelInfo *)f->rev.label, (const int32_t *)nip, MK, K, bk.c > 0 ? blk : -1,
+                           split_e);
+        ScanSource ssrc;
+        ssrc.i32 = split_e;
+        TRY(launch_scan<int64_t>(s, ssrc, MK, tiles, se_off, se_total));
+        const int64_t fix_bound = std::min<int64_t>(split_bound, MK) * (int64_t)std::max(f->rev.max_elems, 1);
+        hipLaunchKernelGGL((counts_fixup<256>), dim3(grid_for(fix_bound, 256, 16384)), dim3(256), 0, s, f->rev,
+                           (const CountItem *)items, (const int32_t *)item_base, (const int32_t *)nip,
+                           (const int64_t *)se_off, (const int64_t *)se_total, (const int32_t *)item_slot,
+                           (const float *)partial, grad_arc_score, caps, MK, K, f->health);
+        return WFST_OK;
+    };
+    if (bk.c == 0) {
+        build_visits();
+        TRY(counts_block(0));
+    } else {
+        for (int32_t k = K - 1; k >= 0; --k) {  // blocks from the end: recompute alpha~, beta sweep, counts
+            bk.k = k;
+            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
+            DISPATCH_NT(rc, f->nt, launch_forward, f, s, bv, tp, bk, nullptr)
+            if (rc != WFST_OK) return rc;
+            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
+            DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk)
+            if (rc != WFST_OK) return rc;
+            build_visits();
+            TRY(counts_block(k));
+        }
+    }
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }

@@ -212,3 +212,38 @@ def test_autograd_final_scores(wf):
     assert np.all(np.abs(theta.grad.cpu().numpy() - ograd) <= 1e-5 * np.maximum(1, n_k))
     nf = final_visits(fst, batch)
     assert np.all(np.abs(fin.grad.cpu().numpy() - ofin) <= 1e-5 * np.maximum(1, nf))
+
+
+def _fb_all(wf, d, batch):
+    import torch
+    lz, post, fpost, st = wf.forward_backward(d, batch.offsets, batch.tokens, final_posteriors=True)
+    torch.cuda.synchronize()
+    assert d.health() == 0, f"kernel health flags {d.health():#x}"
+    return lz.cpu().numpy(), post.cpu().numpy(), fpost.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["tiny", "trigram", "trigram_chunk4"])
+def test_checkpointing(wf, case):
+    """alpha checkpointing (every ceil(sqrt(T_max)) steps, blocks recomputed in
+    the backward pass): log Z and final posteriors bitwise equal to the
+    resident tape, arc posteriors within the oracle tolerance; forced and
+    auto (tiny budget) modes bitwise equal."""
+    if case == "tiny":
+        fst = synth.tiny_random_fst(7, 5, 3, 25, final_prob=0.7)
+        batch = synth.random_batch(7, fst.num_ilabels, np.random.default_rng(7).integers(0, 40, 64))
+        kw = {}
+    else:
+        fst, batch = synth.config(3, vocab=2000, batch=200)
+        kw = {"chunk_arcs": 4} if case == "trigram_chunk4" else {}
+    say(f"case: checkpointing {case}")
+    full = _fb_all(wf, wf.Fst.from_synth(fst, checkpoint=2, **kw), batch)
+    ck = _fb_all(wf, wf.Fst.from_synth(fst, checkpoint=1, **kw), batch)
+    auto = _fb_all(wf, wf.Fst.from_synth(fst, checkpoint=0, tape_budget_bytes=64, **kw), batch)
+    olz, opost, ofin, ost = oracle.forward_backward(fst, batch, final_posteriors=True)
+    n_k = visits_per_arc(fst, batch)
+    for r in (full, ck, auto):
+        np.testing.assert_array_equal(r[3], ost)
+        assert np.all(np.abs(r[1] - opost) <= 1e-5 * np.maximum(1, n_k))
+    assert ck[0].tobytes() == full[0].tobytes(), "log Z differs with checkpointing"
+    assert ck[2].tobytes() == full[2].tobytes(), "final posteriors differ with checkpointing"
+    assert all(a.tobytes() == b.tobytes() for a, b in zip(ck, auto)), "auto and forced checkpointing differ"
