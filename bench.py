@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--per-sentence", type=int, default=512,
                     help="sentences run one per call for the per-sentence form (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="sentences timed on the CPU oracle (0: skip)")
+    ap.add_argument("--threads", type=int, default=0,
+                    help="workgroup size per sentence of the sweeps (64..1024; 0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -144,7 +146,7 @@ def main():
         f"{int(batch.offsets[-1])} symbols ({time.time() - t:.1f} s)")
     log("building the device layouts")
     t = time.time()
-    d = wf.Fst.from_synth(fst)
+    d = wf.Fst.from_synth(fst, threads_per_sentence=args.threads)
     info = d.info()
     log(f"  done in {time.time() - t:.1f} s, {info['device_bytes'] / 2**30:.2f} GiB on device")
 

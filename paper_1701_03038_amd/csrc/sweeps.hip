@@ -1358,8 +1358,14 @@ __global__ void __launch_bounds__(1024) items_by_block(const CountItem *__restri
     }
 }
 
-// new scores into a layout through its element -> arc map
-// (four elements per thread; out and elem_arc are 16-byte aligned allocations)
+// New scores into both layouts through their element -> arc maps.  Each
+// thread writes four consecutive elements; the layouts are concatenated in
+// one index space.  Workgroups are dispatched round-robin over the 8 XCDs:
+// workgroup g is given tile (g % 8) * (tiles / 8) + g / 8, so each XCD walks
+// its own contiguous eighth of the elements and the scores it gathers (arcs of
+// the same labels) stay in its L2.
+constexpr int kXcds = 8;
+
 __device__ __forceinline__ float scatter_one(int arc, const float *__restrict__ score)
 {
     if (arc < 0) return 0.0f;  // padding keeps score 0
@@ -1367,22 +1373,36 @@ __device__ __forceinline__ float scatter_one(int arc, const float *__restrict__ 
     return s == 0.0f ? 0.0f : s;
 }
 
-__global__ void scatter_scores(float *__restrict__ out, const int32_t *__restrict__ elem_arc, int64_t n,
-                               const float *__restrict__ score)
+__device__ __forceinline__ void scatter_range(float *__restrict__ out, const int32_t *__restrict__ elem_arc,
+                                              int64_t n, int64_t e4, const float *__restrict__ score)
 {
-    const int64_t n4 = n / 4;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n4; e += stride) {
-        const int4 a = reinterpret_cast<const int4 *>(elem_arc)[e];
+    const int64_t e = 4 * e4;
+    if (e + 4 <= n) {
+        const int4 a = reinterpret_cast<const int4 *>(elem_arc)[e4];
         float4 v;
         v.x = scatter_one(a.x, score);
         v.y = scatter_one(a.y, score);
         v.z = scatter_one(a.z, score);
         v.w = scatter_one(a.w, score);
-        reinterpret_cast<float4 *>(out)[e] = v;
+        reinterpret_cast<float4 *>(out)[e4] = v;
+    } else {
+        for (int64_t x = e; x < n; ++x) out[x] = scatter_one(elem_arc[x], score);
     }
-    for (int64_t e = 4 * n4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += stride)
-        out[e] = scatter_one(elem_arc[e], score);
+}
+
+// tiles of 256 threads x 4 elements; n4a / n4b = quads of layout a / b (rounded up)
+__global__ void __launch_bounds__(256) scatter_scores(float *__restrict__ out_a, const int32_t *__restrict__ arc_a,
+                                                      int64_t n_a, float *__restrict__ out_b,
+                                                      const int32_t *__restrict__ arc_b, int64_t n_b,
+                                                      const float *__restrict__ score)
+{
+    const int64_t tiles = gridDim.x;  // a multiple of kXcds
+    const int64_t g = blockIdx.x;
+    const int64_t tile = (g % kXcds) * (tiles / kXcds) + g / kXcds;
+    const int64_t q = tile * 256 + threadIdx.x;
+    const int64_t n4a = (n_a + 3) / 4, n4b = (n_b + 3) / 4;
+    if (q < n4a) scatter_range(out_a, arc_a, n_a, q, score);
+    else if (q - n4a < n4b) scatter_range(out_b, arc_b, n_b, q - n4a, score);
 }
 
 __global__ void final_max_kernel(const float *__restrict__ fin, int32_t Q, float *__restrict__ out)

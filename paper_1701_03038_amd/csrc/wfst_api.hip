@@ -772,9 +772,12 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
     hipStream_t s = as_stream(stream);
     if (arc_score_dev && f->A > 0) {
         ProfScope prof(f, s, WFST_KERNEL_SCORES);
-        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->fwd.n_elem / 4 + 1, 256, 8192)), dim3(256), 0, s, f->fwd.score,
-                           (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, arc_score_dev);
-        hipLaunchKernelGGL(scatter_scores, dim3(grid_for(f->rev.n_elem / 4 + 1, 256, 8192)), dim3(256), 0, s, f->rev.score,
+        const int64_t quads = (f->fwd.n_elem + 3) / 4 + (f->rev.n_elem + 3) / 4;
+        int64_t tiles = (quads + 255) / 256;
+        tiles = (tiles + kXcds - 1) / kXcds * kXcds;
+        if (tiles > INT32_MAX) return set_err(WFST_EUNSUPPORTED, "too many arc slots for one score update");
+        hipLaunchKernelGGL(scatter_scores, dim3((unsigned)tiles), dim3(256), 0, s, f->fwd.score,
+                           (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, f->rev.score,
                            (const int32_t *)f->rev.elem_arc, f->rev.n_elem, arc_score_dev);
     }
     if (final_score_dev) {
