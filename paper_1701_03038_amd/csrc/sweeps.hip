@@ -1405,6 +1405,47 @@ __global__ void __launch_bounds__(256) scatter_scores(float *__restrict__ out_a,
     else if (q - n4a < n4b) scatter_range(out_b, arc_b, n_b, q - n4a, score);
 }
 
+// Score update by label (FSTs whose labels have many arcs in compact arc-id
+// ranges): one workgroup per label copies the label's scores into LDS once,
+// then writes both layouts' slots of the label from there, so every score is
+// read from HBM once.  A label whose range exceeds the stage reads directly.
+constexpr int kScoreThreads = 512;
+constexpr int kScoreStage = 12288;  // floats (48 KiB of LDS)
+
+__device__ __forceinline__ void scatter_label_layout(const LabelInfo &li, float *__restrict__ out,
+                                                     const int32_t *__restrict__ elem_arc, const float *stage,
+                                                     int32_t lo, bool staged, const float *__restrict__ score)
+{
+    for (int e = threadIdx.x; e < li.n_elems; e += kScoreThreads) {
+        const int arc = elem_arc[li.elem_first + e];
+        float v = 0.0f;  // padding keeps score 0
+        if (arc >= 0) {
+            v = staged ? stage[arc - lo] : score[arc];
+            v = v == 0.0f ? 0.0f : v;
+        }
+        out[li.elem_first + e] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kScoreThreads)
+scatter_scores_by_label(const LabelInfo *__restrict__ fl, const LabelInfo *__restrict__ rl,
+                        const int2 *__restrict__ range, float *__restrict__ out_f, const int32_t *__restrict__ arc_f,
+                        float *__restrict__ out_r, const int32_t *__restrict__ arc_r,
+                        const float *__restrict__ score)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *stage = reinterpret_cast<float *>(smem);
+    const int a = blockIdx.x;
+    const int2 r = range[a];
+    const int n = r.y - r.x + 1;  // <= 0 for a label without arcs
+    const bool staged = n > 0 && n <= kScoreStage;
+    if (staged)
+        for (int j = threadIdx.x; j < n; j += kScoreThreads) stage[j] = score[r.x + j];
+    __syncthreads();
+    scatter_label_layout(fl[a], out_f, arc_f, stage, r.x, staged, score);
+    scatter_label_layout(rl[a], out_r, arc_r, stage, r.x, staged, score);
+}
+
 __global__ void final_max_kernel(const float *__restrict__ fin, int32_t Q, float *__restrict__ out)
 {
     __shared__ float red[1024];

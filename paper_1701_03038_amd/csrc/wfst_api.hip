@@ -114,6 +114,8 @@ struct wfst_fst {
     float *final_score = nullptr;
     float *final_max = nullptr;
     int32_t *olabel = nullptr;
+    int2 *label_range = nullptr;  // [M] lowest and highest arc id of each label (score updates)
+    bool stage_scores = false;    // score updates staged per label through LDS
     uint32_t *health = nullptr;  // sticky health bits of the kernels (see wfst_fst_health)
     int64_t bytes = 0;
     int cu_count = 0;
@@ -748,6 +750,23 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
             hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t *>(f->health), (int64_t)1, 0);
         if (rc == WFST_OK && olabel) rc = dev_upload(f, &f->olabel, olabel, num_arcs, s);
         if (rc == WFST_OK) {
+            // arc-id range per label; labels with many arcs in a compact range get
+            // their score updates staged through LDS
+            std::vector<int2> range((size_t)num_ilabels, make_int2(INT32_MAX, -1));
+            for (int64_t k = 0; k < num_arcs; ++k) {
+                int2 &r = range[(size_t)ilabel[k]];
+                r.x = std::min(r.x, (int32_t)k);
+                r.y = std::max(r.y, (int32_t)k);
+            }
+            int64_t staged_arcs = 0;
+            for (int32_t a = 0; a < num_ilabels; ++a) {
+                const int2 r = range[(size_t)a];
+                if (r.y >= r.x && (int64_t)r.y - r.x < kScoreStage) staged_arcs += f->label_arcs[(size_t)a];
+            }
+            f->stage_scores = num_arcs > 0 && num_arcs / num_ilabels >= 256 && 2 * staged_arcs >= num_arcs;
+            rc = dev_upload(f, &f->label_range, range.data(), num_ilabels, s);
+        }
+        if (rc == WFST_OK) {
             hipLaunchKernelGGL(final_max_kernel, dim3(1), dim3(1024), 0, s, (const float *)f->final_score, f->Q,
                                f->final_max);
             if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
@@ -776,9 +795,17 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
         int64_t tiles = (quads + 255) / 256;
         tiles = (tiles + kXcds - 1) / kXcds * kXcds;
         if (tiles > INT32_MAX) return set_err(WFST_EUNSUPPORTED, "too many arc slots for one score update");
-        hipLaunchKernelGGL(scatter_scores, dim3((unsigned)tiles), dim3(256), 0, s, f->fwd.score,
-                           (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, f->rev.score,
-                           (const int32_t *)f->rev.elem_arc, f->rev.n_elem, arc_score_dev);
+        if (f->stage_scores) {
+            hipLaunchKernelGGL(scatter_scores_by_label, dim3((unsigned)f->M), dim3(kScoreThreads),
+                               kScoreStage * sizeof(float), s, (const LabelInfo *)f->fwd.label,
+                               (const LabelInfo *)f->rev.label, (const int2 *)f->label_range, f->fwd.score,
+                               (const int32_t *)f->fwd.elem_arc, f->rev.score, (const int32_t *)f->rev.elem_arc,
+                               arc_score_dev);
+        } else {
+            hipLaunchKernelGGL(scatter_scores, dim3((unsigned)tiles), dim3(256), 0, s, f->fwd.score,
+                               (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, f->rev.score,
+                               (const int32_t *)f->rev.elem_arc, f->rev.n_elem, arc_score_dev);
+        }
     }
     if (final_score_dev) {
         hipLaunchKernelGGL(copy_f32, dim3(grid_for(f->Q, 256)), dim3(256), 0, s, f->final_score, final_score_dev,
