@@ -1412,18 +1412,32 @@ __global__ void __launch_bounds__(256) scatter_scores(float *__restrict__ out_a,
 constexpr int kScoreThreads = 512;
 constexpr int kScoreStage = 12288;  // floats (48 KiB of LDS)
 
+constexpr int kScoreUnroll = 8;  // elements per thread in flight
+
 __device__ __forceinline__ void scatter_label_layout(const LabelInfo &li, float *__restrict__ out,
                                                      const int32_t *__restrict__ elem_arc, const float *stage,
                                                      int32_t lo, bool staged, const float *__restrict__ score)
 {
-    for (int e = threadIdx.x; e < li.n_elems; e += kScoreThreads) {
-        const int arc = elem_arc[li.elem_first + e];
-        float v = 0.0f;  // padding keeps score 0
-        if (arc >= 0) {
-            v = staged ? stage[arc - lo] : score[arc];
-            v = v == 0.0f ? 0.0f : v;
+    const int32_t *ea = elem_arc + li.elem_first;
+    float *o = out + li.elem_first;
+    for (int e0 = threadIdx.x; e0 < li.n_elems; e0 += kScoreUnroll * kScoreThreads) {
+        int arc[kScoreUnroll];
+#pragma unroll
+        for (int u = 0; u < kScoreUnroll; ++u) {
+            const int e = e0 + u * kScoreThreads;
+            arc[u] = e < li.n_elems ? ea[e] : -1;
         }
-        out[li.elem_first + e] = v;
+        float v[kScoreUnroll];
+#pragma unroll
+        for (int u = 0; u < kScoreUnroll; ++u) {
+            v[u] = 0.0f;  // padding keeps score 0
+            if (arc[u] >= 0) v[u] = staged ? stage[arc[u] - lo] : score[arc[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kScoreUnroll; ++u) {
+            const int e = e0 + u * kScoreThreads;
+            if (e < li.n_elems) o[e] = v[u] == 0.0f ? 0.0f : v[u];
+        }
     }
 }
 
@@ -1439,8 +1453,21 @@ scatter_scores_by_label(const LabelInfo *__restrict__ fl, const LabelInfo *__res
     const int2 r = range[a];
     const int n = r.y - r.x + 1;  // <= 0 for a label without arcs
     const bool staged = n > 0 && n <= kScoreStage;
-    if (staged)
-        for (int j = threadIdx.x; j < n; j += kScoreThreads) stage[j] = score[r.x + j];
+    if (staged) {
+        for (int j0 = threadIdx.x; j0 < n; j0 += kScoreUnroll * kScoreThreads) {
+            float x[kScoreUnroll];
+#pragma unroll
+            for (int u = 0; u < kScoreUnroll; ++u) {
+                const int j = j0 + u * kScoreThreads;
+                x[u] = j < n ? score[r.x + j] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kScoreUnroll; ++u) {
+                const int j = j0 + u * kScoreThreads;
+                if (j < n) stage[j] = x[u];
+            }
+        }
+    }
     __syncthreads();
     scatter_label_layout(fl[a], out_f, arc_f, stage, r.x, staged, score);
     scatter_label_layout(rl[a], out_r, arc_r, stage, r.x, staged, score);
