@@ -193,11 +193,13 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
         if (tid == 0) val0[start] = VEnt{0.0f, 0};
         __syncthreads();
 
+        LabelInfo li_next = T > 0 ? fl.label[bv.tokens[o0]] : LabelInfo{};
+        LabelInfo lp{};  // label of the previous step (its support is reset)
         for (int t = 1; t <= T; ++t) {
             VEnt *prev = (t & 1) ? val0 : val1;
             VEnt *cur = (t & 1) ? val1 : val0;
-            const int a = bv.tokens[o0 + t - 1];
-            const LabelInfo li = fl.label[a];
+            const LabelInfo li = li_next;
+            if (t < T) li_next = fl.label[bv.tokens[o0 + t]];  // in flight during this step
             const int64_t toff = bv.tok_off[o0 + t - 1];
             // phase 1: one chunk per lane
             for (int s = wave; s < li.n_slices; s += NW) {
@@ -205,6 +207,8 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                 if (lane < si.width) {
                     const int32_t *op = fl.other + si.base + lane;
                     const float *sp = fl.score + si.base + lane;
+                    const int c = s * 64 + lane;
+                    const int dk = c >= li.n_slots ? fl.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)] : 0;
                     float best = WFST_NINF;
                     int bpos = -1, bsrc = 0;
                     for (int r0 = 0; r0 < si.height; r0 += kRowBatch) {
@@ -221,12 +225,11 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                         }
                     }
                     const int pred = bpos >= 0 ? prev[bsrc].idx : -1;
-                    const int c = s * 64 + lane;
                     if (c < li.n_slots) {
                         part[c] = VPart{best, bpos, pred};
                     } else {
                         const int j = li.n_multi + (c - li.n_slots);
-                        const int d = fl.seg_key[li.seg_first + j];
+                        const int d = dk;
                         if (bpos >= 0) cur[d] = VEnt{best, j};
                         bp[toff + j] = make_int2(bpos, pred);
                     }
@@ -249,9 +252,9 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             if (t == 1) {
                 if (tid == 0) prev[start].v = WFST_NINF;
             } else {
-                const LabelInfo lp = fl.label[bv.tokens[o0 + t - 2]];
                 for (int j = tid; j < lp.n_segs; j += NT) prev[fl.seg_key[lp.seg_first + j]].v = WFST_NINF;
             }
+            lp = li;
             __syncthreads();
         }
 
@@ -344,6 +347,7 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
             si[k] = s < li.n_slices ? L.slice[li.slice_first + s] : SliceInfo{0, 0, 0, 0};
         }
         Elem e[SB][RB];
+        int dkey[SB];  // key state of a single-chunk segment, loaded with its rows
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
             const bool on = lane < si[k].width;
@@ -353,6 +357,8 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
             for (int u = 0; u < RB; ++u)
                 e[k][u] = on && u < si[k].height ? Elem{op[u * si[k].width], sp[u * si[k].width]}
                                                  : Elem{dead, 0.0f};
+            const int c = (s0 + k * NW) * 64 + lane;
+            dkey[k] = on && c >= li.n_slots ? L.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)] : 0;
         }
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
@@ -382,7 +388,7 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
                     part[c] = acc;
                 } else {
                     const int j = li.n_multi + (c - li.n_slots);
-                    const int d = L.seg_key[li.seg_first + j];
+                    const int d = dkey[k];
                     const float v = lse_value(acc);
                     cur[d] = v;
                     if (tape) tape[j] = v;
@@ -495,11 +501,14 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
         }
         __syncthreads();
         double C = 0.0;  // log scale of alpha (thread 0)
+        LabelInfo li_next = t1 > t0 ? fl.label[bv.tokens[o0 + t0]] : LabelInfo{};
+        LabelInfo lp = t0 > 0 ? fl.label[bv.tokens[o0 + t0 - 1]] : LabelInfo{};
         for (int t = t0 + 1; t <= t1; ++t) {
             float *prev = (t & 1) ? val0 : val1;
             float *cur = (t & 1) ? val1 : val0;
             const int i = o0 + t - 1;
-            const LabelInfo li = fl.label[bv.tokens[i]];
+            const LabelInfo li = li_next;
+            if (t < t1) li_next = fl.label[bv.tokens[i + 1]];  // in flight during this step
             float *tape;
             if (bk.c > 0) {
                 int blk;
@@ -513,9 +522,9 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
-                const LabelInfo lp = fl.label[bv.tokens[i - 1]];
                 for (int j = tid; j < lp.n_segs; j += NT) prev[fl.seg_key[lp.seg_first + j]] = WFST_NINF;
             }
+            lp = li;
             if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
             block_max_into(mx, &s_cmax[t % 3], lane);
             __syncthreads();
@@ -649,18 +658,30 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         if (tid < 3) s_cmax[tid] = 0u;
         __syncthreads();
+        int a_next = bv.tokens[o0 + t1 - 1];
+        LabelInfo li_next = rl.label[a_next];
+        LabelInfo lp{};  // reverse label of step t+1 (its support is reset)
         for (int t = t1; t > t0; --t) {
             float *prev = (t & 1) ? val1 : val0;  // beta~_t
             float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
             const int i = o0 + t - 1;
-            const LabelInfo li = rl.label[bv.tokens[i]];
+            const LabelInfo li = li_next;
+            // in flight during this step: the labels of token i-1 and the keys of its tape entries
+            LabelInfo lf{};
+            int tkey = 0;
+            if (t >= 2) {
+                a_next = bv.tokens[i - 1];
+                li_next = rl.label[a_next];
+                lf = fl.label[a_next];
+                if (tid < lf.n_segs) tkey = fl.seg_key[lf.seg_first + tid];
+            }
             const float mx = lse_step<NT, 4, 4>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave, Q);
-            const LabelInfo lp = rl.label[bv.tokens[t == T ? i : i + 1]];
             if (t == t1 || 4 * lp.n_segs >= Q) {  // first step or wide support: clear the whole vector
                 for (int q = tid; q < Q; q += NT) prev[q] = WFST_NINF;
             } else {
                 for (int j = tid; j < lp.n_segs; j += NT) prev[rl.seg_key[lp.seg_first + j]] = WFST_NINF;
             }
+            lp = li;
             if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
             block_max_into(mx, &s_cmax[t % 3], lane);
             __syncthreads();
@@ -668,9 +689,9 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             if (!(c > WFST_NINF)) c = 0.0f;
             if (tid == 0) C += (double)c;
             if (t >= 2) {
-                const LabelInfo lf = fl.label[bv.tokens[i - 1]];
                 float *tape = beta_slot(tp, bk, bv, b, o0, i - 1);
-                for (int j = tid; j < lf.n_segs; j += NT) tape[j] = cur[fl.seg_key[lf.seg_first + j]];
+                if (tid < lf.n_segs) tape[tid] = cur[tkey];
+                for (int j = tid + NT; j < lf.n_segs; j += NT) tape[j] = cur[fl.seg_key[lf.seg_first + j]];
                 if (tid == 0) {
                     tp.b_max[i - 1] = c;
                     tp.b_log[i - 1] = C;
