@@ -48,22 +48,68 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(fst_dev, tokens):
-    """Bytes each kernel must move per launch (one batch), from the per-symbol
-    figures: Viterbi 8A+12D (arcs {state, score}, segment table, back-pointer),
-    forward 8A+8D, backward 8A+8D' over the reverse layout, counts 16A per
-    label present (arcs {src, score}, their segment, gradient write), score
-    scatter 24A (two layouts), gradient fill 4A.  A, D, D' are the arcs,
-    destination segments and source segments of the symbol's label."""
+def live_arcs(fst, batch):
+    """Per token (b, t) with label a and previous label p (the start state at
+    t = 1): L = number of arcs with input a leaving a state p can reach, i.e.
+    the arcs whose source alpha_{t-1} can occupy.  Cached per (p, a)."""
+    import numpy as np
+    il = fst.ilabel
+    if np.all(il[1:] >= il[:-1]):
+        order = None
+        start = np.searchsorted(il, np.arange(fst.num_ilabels + 1))
+    else:
+        order = np.argsort(il, kind="stable")
+        start = np.searchsorted(il[order], np.arange(fst.num_ilabels + 1))
+
+    def arcs_of(a):
+        sl = slice(start[a], start[a + 1])
+        return sl if order is None else order[sl]
+
+    dsts, cache = {}, {}
+    L = np.zeros(batch.tokens.size, np.int64)
+    offs = batch.offsets
+    for bi in range(batch.size):
+        for i in range(int(offs[bi]), int(offs[bi + 1])):
+            a = int(batch.tokens[i])
+            p = int(batch.tokens[i - 1]) if i > offs[bi] else -1
+            key = (p, a)
+            if key not in cache:
+                if p not in dsts:
+                    dsts[p] = np.array([fst.start]) if p < 0 else np.unique(fst.dst[arcs_of(p)])
+                cache[key] = int(np.isin(fst.src[arcs_of(a)], dsts[p], assume_unique=False).sum())
+            L[i] = cache[key]
+    return L
+
+
+def algorithmic_bytes(fst_dev, fst, batch):
+    """Bytes each kernel must move per launch (one batch).  A, D, D' are the
+    arcs, destination segments and source segments of a label; L the arcs of
+    the token's label leaving states the previous step can reach; p the
+    previous token's label.
+      Viterbi 8A + 12D (arcs {state, score}, segment table, back-pointer),
+      forward 8A + 8D (arcs, segment table, tape write), per token;
+      backward 4D'(a) + 8L + 8D(p) per token (source keys of the label, the
+        arcs of the marked segments, keys and tape of the states computed);
+      counts 8A + 4D' per work item (arc ids and gradient writes, source keys)
+        plus 8D(p) + 8D(a) + 8L per visit (alpha, beta and their keys, live arcs);
+      score scatter 24 per arc (two layouts: arc id, score read, score write),
+      gradient fill 4 per arc."""
     import numpy as np
     arcs, dseg, rseg = (x.astype(np.int64) for x in fst_dev.label_stats())
+    tokens = batch.tokens
     A_tot = int(arcs.sum())
-    present = np.unique(tokens)
+    first = np.zeros(tokens.size, bool)
+    first[batch.offsets[:-1][batch.lengths() > 0]] = True
+    prev = np.roll(tokens, 1)
+    d_prev = np.where(first, 1, dseg[prev])
+    L = live_arcs(fst, batch)
+    n_vis = np.bincount(tokens, minlength=arcs.size)
+    n_items = (n_vis + 63) // 64
     return {
         "viterbi": float((8 * arcs[tokens] + 12 * dseg[tokens]).sum()),
         "forward": float((8 * arcs[tokens] + 8 * dseg[tokens]).sum()),
-        "backward": float((8 * arcs[tokens] + 8 * rseg[tokens]).sum()),
-        "counts": float(16 * arcs[present].sum()),
+        "backward": float((4 * rseg[tokens] + 8 * L + 8 * d_prev).sum()),
+        "counts": float((n_items * (8 * arcs + 4 * rseg)).sum() + (8 * d_prev + 8 * dseg[tokens] + 8 * L).sum()),
         "scores": float(24 * A_tot),
         "grad_fill": float(4 * A_tot),
     }
@@ -186,7 +232,7 @@ def main():
     d.profile(False)
     health = d.health()
 
-    bytes_per = algorithmic_bytes(d, batch.tokens)
+    bytes_per = algorithmic_bytes(d, fst, batch)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:

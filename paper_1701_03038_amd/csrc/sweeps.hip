@@ -580,23 +580,43 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     }
 }
 
+// Backward pass (paper, Algorithm 2 second loop, with the index typos fixed):
+// beta_{t-1}[s] = LSE over the arcs k with input w_t leaving s of
+// theta_k + beta_t[dst_k].  beta_{t-1} is only ever read on the states
+// alpha_{t-1} can occupy -- the destinations of w_{t-1} (the start state at
+// t = 1): the expected counts pair it with alpha_{t-1}, and step t-1 reads
+// beta_{t-1} only at destinations of w_{t-1}.  So each step marks those
+// states, scans the reverse segments of w_t (one per source state) for marked
+// sources, and reduces just those segments, one thread per segment with its
+// arcs in layout order.  The values on the marked states are the sums a full
+// sweep computes; only the per-step normaliser (the max over the computed
+// states) is taken over fewer states.  The next step's labels and segment keys
+// are loaded while the current step runs.
+constexpr int kSliceCache = 64;  // slice headers of the step's label staged in LDS
+
+constexpr int rev_key_prefetch(int nt) { return nt >= 1024 ? 3 : nt >= 512 ? 5 : 9; }
+constexpr int kTapeKeyPrefetch = 2;
+
 template <int NT>
 __global__ void __launch_bounds__(NT)
 backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                const float *__restrict__ final_score, const float *__restrict__ final_max,
-               BatchView bv, TapeView tp, BlockView bk)
+               BatchView bv, TapeView tp, BlockView bk, int32_t list_cap)
 {
-    constexpr int NW = NT / 64;
+    constexpr int RPF = rev_key_prefetch(NT);
+    constexpr int TPF = kTapeKeyPrefetch;
+    constexpr int RB = 8;
     extern __shared__ __align__(16) unsigned char smem[];
-    float *val0 = reinterpret_cast<float *>(smem);
-    float *val1 = val0 + (Q + 1);
-    Lse *part = reinterpret_cast<Lse *>(val1 + (Q + 1));  // 2(Q+1) floats: 8-byte aligned
-    __shared__ int s_item;
+    SliceInfo *scache = reinterpret_cast<SliceInfo *>(smem);           // [kSliceCache]
+    float *val0 = reinterpret_cast<float *>(scache + kSliceCache);     // [Q+1]
+    float *val1 = val0 + (Q + 1);                                      // [Q+1]
+    int32_t *mark = reinterpret_cast<int32_t *>(val1 + (Q + 1));       // [Q+1] step stamp of states to compute
+    int2 *list = reinterpret_cast<int2 *>(mark + (Q + 1) + ((Q + 1) & 1));  // [list_cap] {segment, key}
+    __shared__ int s_item, s_count;
     __shared__ uint32_t s_cmax[3];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = wave_uniform(tid >> 6);
     const float fmax0 = *final_max;
 
     for (int pops = 0;; ++pops) {
@@ -625,14 +645,15 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         float *vT = (t1 & 1) ? val1 : val0;
         float *vO = (t1 & 1) ? val0 : val1;
+        for (int q = tid; q <= Q; q += NT) {
+            vT[q] = (t1 == T && q < Q) ? final_score[q] : WFST_NINF;
+            vO[q] = WFST_NINF;
+            mark[q] = -1;
+        }
+        __syncthreads();
         float c_prev;
         double C;
         if (t1 == T) {
-            for (int q = tid; q <= Q; q += NT) {
-                vT[q] = q < Q ? final_score[q] : WFST_NINF;
-                vO[q] = WFST_NINF;
-            }
-            __syncthreads();
             // beta_T on the destinations of w_T, for the expected counts
             const LabelInfo lf = fl.label[bv.tokens[o1 - 1]];
             float *tape = beta_slot(tp, bk, bv, b, o0, o1 - 1);
@@ -644,11 +665,6 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             c_prev = fmax0;
             C = (double)fmax0;
         } else {  // resume from beta~_{t1} kept by the previous (later) block
-            for (int q = tid; q <= Q; q += NT) {
-                vT[q] = WFST_NINF;
-                vO[q] = WFST_NINF;
-            }
-            __syncthreads();
             const int i1 = o0 + t1 - 1;
             const LabelInfo lf = fl.label[bv.tokens[i1]];
             const float *tape = beta_slot(tp, bk, bv, b, o0, i1);
@@ -657,41 +673,153 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             C = tp.b_log[i1];
         }
         if (tid < 3) s_cmax[tid] = 0u;
+
+        // labels and keys of step t1, then loaded one step ahead
+        LabelInfo li = rl.label[bv.tokens[o0 + t1 - 1]];  // reverse label of w_t
+        int rk[RPF];                                       // its segment keys (source states)
+#pragma unroll
+        for (int u = 0; u < RPF; ++u) {
+            const int j = tid + u * NT;
+            rk[u] = j < li.n_segs ? rl.seg_key[li.seg_first + j] : -1;
+        }
+        LabelInfo lf{};  // forward label of w_{t-1}: the states to compute
+        int tk[TPF];
+#pragma unroll
+        for (int u = 0; u < TPF; ++u) tk[u] = -1;
+        if (t1 >= 2) {
+            lf = fl.label[bv.tokens[o0 + t1 - 2]];
+#pragma unroll
+            for (int u = 0; u < TPF; ++u) {
+                const int j = tid + u * NT;
+                if (j < lf.n_segs) tk[u] = fl.seg_key[lf.seg_first + j];
+            }
+        }
+        LabelInfo lf_prev{};  // forward label of w_t: support of beta~_t, reset after the step
+        int tk_prev[TPF];
+#pragma unroll
+        for (int u = 0; u < TPF; ++u) tk_prev[u] = -1;
         __syncthreads();
-        int a_next = bv.tokens[o0 + t1 - 1];
-        LabelInfo li_next = rl.label[a_next];
-        LabelInfo lp{};  // reverse label of step t+1 (its support is reset)
+
         for (int t = t1; t > t0; --t) {
             float *prev = (t & 1) ? val1 : val0;  // beta~_t
             float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
             const int i = o0 + t - 1;
-            const LabelInfo li = li_next;
-            // in flight during this step: the labels of token i-1 and the keys of its tape entries
-            LabelInfo lf{};
-            int tkey = 0;
+            // A: mark the states of step t-1, stage the slice headers of w_t
             if (t >= 2) {
-                a_next = bv.tokens[i - 1];
-                li_next = rl.label[a_next];
-                lf = fl.label[a_next];
-                if (tid < lf.n_segs) tkey = fl.seg_key[lf.seg_first + tid];
+#pragma unroll
+                for (int u = 0; u < TPF; ++u)
+                    if (tk[u] >= 0) mark[tk[u]] = t;
+                for (int j = tid + TPF * NT; j < lf.n_segs; j += NT) mark[fl.seg_key[lf.seg_first + j]] = t;
+            } else if (tid == 0) {
+                mark[start] = t;
             }
-            const float mx = lse_step<NT, 4, 4>(rl, li, prev, cur, c_prev, part, nullptr, lane, wave, Q);
-            if (t == t1 || 4 * lp.n_segs >= Q) {  // first step or wide support: clear the whole vector
+            for (int s = tid; s < min(li.n_slices, kSliceCache); s += NT) scache[s] = rl.slice[li.slice_first + s];
+            if (tid == 0) s_count = 0;
+            __syncthreads();
+            // next step's labels and keys, in flight during this step
+            LabelInfo li_n{}, lf_n{};
+            int rk_n[RPF], tk_n[TPF];
+#pragma unroll
+            for (int u = 0; u < RPF; ++u) rk_n[u] = -1;
+#pragma unroll
+            for (int u = 0; u < TPF; ++u) tk_n[u] = -1;
+            if (t - 1 > t0) {
+                li_n = rl.label[bv.tokens[i - 1]];
+#pragma unroll
+                for (int u = 0; u < RPF; ++u) {
+                    const int j = tid + u * NT;
+                    if (j < li_n.n_segs) rk_n[u] = rl.seg_key[li_n.seg_first + j];
+                }
+                if (t - 1 >= 2) {
+                    lf_n = fl.label[bv.tokens[i - 2]];
+#pragma unroll
+                    for (int u = 0; u < TPF; ++u) {
+                        const int j = tid + u * NT;
+                        if (j < lf_n.n_segs) tk_n[u] = fl.seg_key[lf_n.seg_first + j];
+                    }
+                }
+            }
+            // B: reverse segments of w_t whose source is marked
+#pragma unroll
+            for (int u = 0; u < RPF; ++u) {
+                if (rk[u] >= 0 && mark[rk[u]] == t) {
+                    const int pos = atomicAdd(&s_count, 1);
+                    if (pos < list_cap) list[pos] = make_int2(tid + u * NT, rk[u]);
+                }
+            }
+            for (int j = tid + RPF * NT; j < li.n_segs; j += NT) {
+                const int key = rl.seg_key[li.seg_first + j];
+                if (mark[key] == t) {
+                    const int pos = atomicAdd(&s_count, 1);
+                    if (pos < list_cap) list[pos] = make_int2(j, key);
+                }
+            }
+            __syncthreads();
+            int n = s_count;
+            if (n > list_cap) {
+                if (tid == 0) atomicOr(bv.health, H_GROUP);
+                n = list_cap;
+            }
+            // C: one thread per marked segment, its chunks and rows in layout order
+            float my_max = WFST_NINF;
+            for (int x = tid; x < n; x += NT) {
+                const int2 jk = list[x];
+                const int j = jk.x;
+                int c0, nc;
+                if (j < li.n_multi) {
+                    const SegChunk sc = rl.seg_chunk[li.seg_first + j];
+                    c0 = sc.first;
+                    nc = sc.count;
+                } else {
+                    c0 = li.n_slots + (j - li.n_multi);
+                    nc = 1;
+                }
+                Lse acc{WFST_NINF, 0.0f};
+                for (int c = c0; c < c0 + nc; ++c) {
+                    const int s = c >> 6, l = c & 63;
+                    const SliceInfo si = s < kSliceCache ? scache[s] : rl.slice[li.slice_first + s];
+                    for (int r0 = 0; r0 < si.height; r0 += RB) {
+                        Elem e[RB];
+#pragma unroll
+                        for (int u = 0; u < RB; ++u) {
+                            const int pos = si.base + (r0 + u) * si.width + l;
+                            e[u] = r0 + u < si.height ? Elem{rl.other[pos], rl.score[pos]} : Elem{Q, 0.0f};
+                        }
+#pragma unroll
+                        for (int u = 0; u < RB; ++u) {
+                            const float g = prev[e[u].other];
+                            if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e[u].score);
+                        }
+                    }
+                }
+                const float v = lse_value(acc);
+                cur[jk.y] = v;
+                my_max = fmaxf(my_max, v);
+            }
+            if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
+            block_max_into(my_max, &s_cmax[t % 3], lane);
+            __syncthreads();
+            // no thread reads beta~_t any more: clear its support (everything at
+            // the first step); the buffer is written again after the next step's
+            // first barrier
+            if (t == t1) {
                 for (int q = tid; q < Q; q += NT) prev[q] = WFST_NINF;
             } else {
-                for (int j = tid; j < lp.n_segs; j += NT) prev[rl.seg_key[lp.seg_first + j]] = WFST_NINF;
+#pragma unroll
+                for (int u = 0; u < TPF; ++u)
+                    if (tk_prev[u] >= 0) prev[tk_prev[u]] = WFST_NINF;
+                for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
+                    prev[fl.seg_key[lf_prev.seg_first + j]] = WFST_NINF;
             }
-            lp = li;
-            if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
-            block_max_into(mx, &s_cmax[t % 3], lane);
-            __syncthreads();
             float c = unord_f32(s_cmax[t % 3]);
             if (!(c > WFST_NINF)) c = 0.0f;
             if (tid == 0) C += (double)c;
             if (t >= 2) {
                 float *tape = beta_slot(tp, bk, bv, b, o0, i - 1);
-                if (tid < lf.n_segs) tape[tid] = cur[tkey];
-                for (int j = tid + NT; j < lf.n_segs; j += NT) tape[j] = cur[fl.seg_key[lf.seg_first + j]];
+#pragma unroll
+                for (int u = 0; u < TPF; ++u)
+                    if (tk[u] >= 0) tape[tid + u * NT] = cur[tk[u]];
+                for (int j = tid + TPF * NT; j < lf.n_segs; j += NT) tape[j] = cur[fl.seg_key[lf.seg_first + j]];
                 if (tid == 0) {
                     tp.b_max[i - 1] = c;
                     tp.b_log[i - 1] = C;
@@ -701,6 +829,15 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 tp.log_z_bwd[b] = x == WFST_NINF ? -__builtin_huge_val() : C + (double)(x - c);
             }
             c_prev = c;
+            lf_prev = lf;
+#pragma unroll
+            for (int u = 0; u < TPF; ++u) tk_prev[u] = tk[u];
+            li = li_n;
+            lf = lf_n;
+#pragma unroll
+            for (int u = 0; u < RPF; ++u) rk[u] = rk_n[u];
+#pragma unroll
+            for (int u = 0; u < TPF; ++u) tk[u] = tk_n[u];
         }
         __syncthreads();
     }

@@ -238,10 +238,19 @@ struct ProfScope {
     }
 };
 
+// Marked segments per backward step: at most the destinations of one label.
+int32_t backward_list_cap(const wfst_fst *f) { return std::max(f->fwd.max_segs, 1); }
+
 // LDS bytes of each kernel for this FST.
 size_t lds_viterbi(const wfst_fst *f)
 {
     return (size_t)(f->Q + 1) * 2 * sizeof(VEnt) + (size_t)std::max(f->fwd.max_slots, 1) * sizeof(VPart);
+}
+size_t lds_backward(const wfst_fst *f)
+{
+    const size_t q1 = (size_t)f->Q + 1;
+    return kSliceCache * sizeof(SliceInfo) + 2 * q1 * sizeof(float) + (q1 + (q1 & 1)) * sizeof(int32_t) +
+           (size_t)backward_list_cap(f) * sizeof(int2);
 }
 size_t lds_lse(const wfst_fst *f, const DevLayout &l)
 {
@@ -436,12 +445,13 @@ int launch_forward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const 
 template <int NT>
 int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk)
 {
-    const size_t lds = lds_lse(f, f->rev);
+    const size_t lds = lds_backward(f);
     int grid = 0;
     TRY(persistent_grid(f, backward_sweep<NT>, NT, lds, bv.B, &grid));
     ProfScope prof(f, s, WFST_KERNEL_BACKWARD);
     hipLaunchKernelGGL((backward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start,
-                       (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk);
+                       (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
+                       backward_list_cap(f));
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
