@@ -67,7 +67,9 @@ typedef struct wfst_options {
     int32_t checkpoint;         /* forward tape: -1/0 = auto, 1 = force sqrt(T) checkpointing, 2 = never */
     int32_t reserved0;
     int64_t tape_budget_bytes;  /* auto mode checkpoints when the full tape exceeds this; 0 = 8 GiB */
-    int64_t reserved1;
+    int64_t count_records;      /* expected counts: 0 = auto (per-visit records of the backward pass, sorted
+                                   and summed per arc, while they fit; else the label-grouped count kernel),
+                                   -1 = always the grouped count kernel, > 0 = record capacity per call */
 } wfst_options;
 
 /* Layout statistics (for tuning and reporting). */

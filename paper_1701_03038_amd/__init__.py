@@ -41,7 +41,7 @@ class WfstError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("chunk_arcs", ctypes.c_int32), ("threads_per_sentence", ctypes.c_int32),
                 ("checkpoint", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("tape_budget_bytes", ctypes.c_int64), ("reserved1", ctypes.c_int64)]
+                ("tape_budget_bytes", ctypes.c_int64), ("count_records", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):
@@ -146,7 +146,8 @@ class Fst:
     """Device layouts of one WFST (library-owned; freed by close())."""
 
     def __init__(self, num_states, num_ilabels, start, src, dst, ilabel, arc_score, final_score,
-                 olabel=None, chunk_arcs=0, threads_per_sentence=0, checkpoint=0, tape_budget_bytes=0):
+                 olabel=None, chunk_arcs=0, threads_per_sentence=0, checkpoint=0, tape_budget_bytes=0,
+                 count_records=0):
         import torch
         lib = load_library()
         self.num_states, self.num_ilabels, self.start = int(num_states), int(num_ilabels), int(start)
@@ -155,7 +156,7 @@ class Fst:
         sc = np.ascontiguousarray(arc_score, np.float32)
         fin = np.ascontiguousarray(final_score, np.float32)
         self.num_arcs = int(arrs[0].shape[0])
-        opt = _Options(chunk_arcs, threads_per_sentence, checkpoint, 0, tape_budget_bytes, 0)
+        opt = _Options(chunk_arcs, threads_per_sentence, checkpoint, 0, tape_budget_bytes, count_records)
         self.device = torch.cuda.current_device()
         h = ctypes.c_void_p()
         _check(lib.wfst_fst_create(self.num_states, self.num_ilabels, self.start, self.num_arcs,

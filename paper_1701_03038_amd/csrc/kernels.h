@@ -85,6 +85,29 @@ __device__ __forceinline__ int64_t block_rel(const BlockView &bk, const BatchVie
     return bk.base[b] + (bv.tok_off[i] - bv.tok_off[o0 + blk * bk.c]);
 }
 
+// alpha~ of token i: the full tape, a checkpoint, or the block buffer of the
+// token's block (recomputed by the current block's forward pass)
+__device__ __forceinline__ const float *alpha_slot(const TapeView &tp, const BlockView &bk, const BatchView &bv,
+                                                   int b, int o0, int i)
+{
+    if (bk.c == 0) return tp.alpha + bv.tok_off[i];
+    if (tp.ck_off[i] >= 0) return tp.alpha + tp.ck_off[i];
+    int blk;
+    const int64_t r = block_rel(bk, bv, b, o0, i, blk);
+    return bk.abuf[blk & 1] + r;
+}
+
+// Expected-count records written by the backward pass: one per (arc, visit)
+// with a nonzero posterior, key = (arc << 32) | token position.  count may
+// pass cap: records beyond cap are dropped and the caller falls back.
+struct RecordSink {
+    uint64_t *key = nullptr;  // null: no records
+    float *val = nullptr;
+    unsigned long long *count = nullptr;
+    int64_t cap = 0;
+    const float *grad_log_z = nullptr;  // g_b (null = 1)
+};
+
 // beta~ of token i: the full tape, or the block buffer of the token's block
 __device__ __forceinline__ float *beta_slot(const TapeView &tp, const BlockView &bk, const BatchView &bv, int b,
                                             int o0, int i)

@@ -140,7 +140,8 @@ __global__ void __launch_bounds__(1024) order_by_length(const int32_t *__restric
 }
 
 // ---------------------------------------------------------------------
-// Stable LSD radix sort of (key, value) int32 pairs, 8 bits per pass.
+// Stable LSD radix sort of (key, value) pairs (int32 or uint64 keys, int32
+// values), 8 bits per pass.
 // Tile = 1024 elements per block of 256 threads (4 per thread, consecutive).
 // ---------------------------------------------------------------------
 constexpr int kSortThreads = 256;
@@ -148,9 +149,11 @@ constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 __device__ __forceinline__ int digit_of(int32_t key, int shift) { return ((uint32_t)key >> shift) & 0xff; }
+__device__ __forceinline__ int digit_of(uint64_t key, int shift) { return (int)((key >> shift) & 0xff); }
 
 // hist[d * ntiles + tile] = occurrences of digit d in the tile
-__global__ void __launch_bounds__(kSortThreads) radix_hist(const int32_t *__restrict__ keys, int64_t n, int shift,
+template <class K>
+__global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                            int64_t ntiles, int64_t *__restrict__ hist)
 {
     __shared__ int h[256];
@@ -169,11 +172,12 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist(const int32_t *__rest
 // tile owns elements [256w, 256w+256) in four rounds of 64 consecutive
 // elements; a lane's rank among equal digits before it comes from matching
 // its digit against the wave with 8 ballots, so every pass is stable.
-__global__ void __launch_bounds__(kSortThreads) radix_scatter(const int32_t *__restrict__ keys_in,
+template <class K>
+__global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restrict__ keys_in,
                                                               const int32_t *__restrict__ vals_in, int64_t n,
                                                               int shift, int64_t ntiles,
                                                               const int64_t *__restrict__ offs,
-                                                              int32_t *__restrict__ keys_out,
+                                                              K *__restrict__ keys_out,
                                                               int32_t *__restrict__ vals_out,
                                                               uint32_t *__restrict__ health)
 {
@@ -185,7 +189,8 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const int32_t *__r
     const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * 256;
     const unsigned long long lt = (1ull << lane) - 1ull;
     int dg[kSortItems], rank[kSortItems];
-    int32_t kv[kSortItems], vv[kSortItems];
+    K kv[kSortItems];
+    int32_t vv[kSortItems];
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = base + k * 64 + lane;
         const bool valid = i < n;

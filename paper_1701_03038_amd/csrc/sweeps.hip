@@ -601,7 +601,7 @@ template <int NT>
 __global__ void __launch_bounds__(NT)
 backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                const float *__restrict__ final_score, const float *__restrict__ final_max,
-               BatchView bv, TapeView tp, BlockView bk, int32_t list_cap)
+               BatchView bv, TapeView tp, BlockView bk, int32_t list_cap, RecordSink rs)
 {
     constexpr int RPF = rev_key_prefetch(NT);
     constexpr int TPF = kTapeKeyPrefetch;
@@ -611,7 +611,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     float *val0 = reinterpret_cast<float *>(scache + kSliceCache);     // [Q+1]
     float *val1 = val0 + (Q + 1);                                      // [Q+1]
     int32_t *mark = reinterpret_cast<int32_t *>(val1 + (Q + 1));       // [Q+1] step stamp of states to compute
-    int2 *list = reinterpret_cast<int2 *>(mark + (Q + 1) + ((Q + 1) & 1));  // [list_cap] {segment, key}
+    float *aval = reinterpret_cast<float *>(mark + (Q + 1));           // [Q+1] alpha~_{t-1} - c_{t-1} there
+    int2 *list = reinterpret_cast<int2 *>(aval + (Q + 1));             // [list_cap] {segment, key}
     __shared__ int s_item, s_count;
     __shared__ uint32_t s_cmax[3];
 
@@ -673,6 +674,9 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             C = tp.b_log[i1];
         }
         if (tid < 3) s_cmax[tid] = 0u;
+        const bool rec = rs.key != nullptr;
+        const float gb = rs.grad_log_z ? rs.grad_log_z[b] : 1.0f;
+        const double lz = tp.log_z[b];
 
         // labels and keys of step t1, then loaded one step ahead
         LabelInfo li = rl.label[bv.tokens[o0 + t1 - 1]];  // reverse label of w_t
@@ -684,14 +688,26 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         LabelInfo lf{};  // forward label of w_{t-1}: the states to compute
         int tk[TPF];
+        float ta[TPF];   // alpha~_{t-1} - c_{t-1} on them (records only)
+        double aC = 0.0; // log scale of alpha_{t-1}
 #pragma unroll
-        for (int u = 0; u < TPF; ++u) tk[u] = -1;
+        for (int u = 0; u < TPF; ++u) {
+            tk[u] = -1;
+            ta[u] = WFST_NINF;
+        }
         if (t1 >= 2) {
-            lf = fl.label[bv.tokens[o0 + t1 - 2]];
+            const int ip = o0 + t1 - 2;
+            lf = fl.label[bv.tokens[ip]];
+            const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
+            const float cm = rec ? tp.a_max[ip] : 0.0f;
+            if (rec) aC = tp.a_log[ip];
 #pragma unroll
             for (int u = 0; u < TPF; ++u) {
                 const int j = tid + u * NT;
-                if (j < lf.n_segs) tk[u] = fl.seg_key[lf.seg_first + j];
+                if (j < lf.n_segs) {
+                    tk[u] = fl.seg_key[lf.seg_first + j];
+                    if (rec) ta[u] = ap[j] - cm;
+                }
             }
         }
         LabelInfo lf_prev{};  // forward label of w_t: support of beta~_t, reset after the step
@@ -704,25 +720,45 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             float *prev = (t & 1) ? val1 : val0;  // beta~_t
             float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
             const int i = o0 + t - 1;
-            // A: mark the states of step t-1, stage the slice headers of w_t
+            // A: mark the states of step t-1 (with alpha~_{t-1} for the records),
+            // stage the slice headers of w_t
             if (t >= 2) {
 #pragma unroll
                 for (int u = 0; u < TPF; ++u)
-                    if (tk[u] >= 0) mark[tk[u]] = t;
-                for (int j = tid + TPF * NT; j < lf.n_segs; j += NT) mark[fl.seg_key[lf.seg_first + j]] = t;
+                    if (tk[u] >= 0) {
+                        mark[tk[u]] = t;
+                        aval[tk[u]] = ta[u];
+                    }
+                if (lf.n_segs > TPF * NT) {
+                    const int ip = i - 1;
+                    const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
+                    const float cm = rec ? tp.a_max[ip] : 0.0f;
+                    for (int j = tid + TPF * NT; j < lf.n_segs; j += NT) {
+                        const int q = fl.seg_key[lf.seg_first + j];
+                        mark[q] = t;
+                        aval[q] = rec ? ap[j] - cm : WFST_NINF;
+                    }
+                }
             } else if (tid == 0) {
                 mark[start] = t;
+                aval[start] = 0.0f;  // alpha~_0 = 0 at the start state, no normaliser
             }
+            const float o = rec ? (float)((t >= 2 ? aC : 0.0) + C - lz) : 0.0f;  // C = log scale of beta_t
             for (int s = tid; s < min(li.n_slices, kSliceCache); s += NT) scache[s] = rl.slice[li.slice_first + s];
             if (tid == 0) s_count = 0;
             __syncthreads();
             // next step's labels and keys, in flight during this step
             LabelInfo li_n{}, lf_n{};
             int rk_n[RPF], tk_n[TPF];
+            float ta_n[TPF];
+            double aC_n = 0.0;
 #pragma unroll
             for (int u = 0; u < RPF; ++u) rk_n[u] = -1;
 #pragma unroll
-            for (int u = 0; u < TPF; ++u) tk_n[u] = -1;
+            for (int u = 0; u < TPF; ++u) {
+                tk_n[u] = -1;
+                ta_n[u] = WFST_NINF;
+            }
             if (t - 1 > t0) {
                 li_n = rl.label[bv.tokens[i - 1]];
 #pragma unroll
@@ -731,11 +767,18 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     if (j < li_n.n_segs) rk_n[u] = rl.seg_key[li_n.seg_first + j];
                 }
                 if (t - 1 >= 2) {
-                    lf_n = fl.label[bv.tokens[i - 2]];
+                    const int ip = i - 2;
+                    lf_n = fl.label[bv.tokens[ip]];
+                    const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
+                    const float cm = rec ? tp.a_max[ip] : 0.0f;
+                    if (rec) aC_n = tp.a_log[ip];
 #pragma unroll
                     for (int u = 0; u < TPF; ++u) {
                         const int j = tid + u * NT;
-                        if (j < lf_n.n_segs) tk_n[u] = fl.seg_key[lf_n.seg_first + j];
+                        if (j < lf_n.n_segs) {
+                            tk_n[u] = fl.seg_key[lf_n.seg_first + j];
+                            if (rec) ta_n[u] = ap[j] - cm;
+                        }
                     }
                 }
             }
@@ -774,6 +817,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     c0 = li.n_slots + (j - li.n_multi);
                     nc = 1;
                 }
+                const float a = rec ? aval[jk.y] : WFST_NINF;  // alpha~_{t-1} - c_{t-1} at the source
                 Lse acc{WFST_NINF, 0.0f};
                 for (int c = c0; c < c0 + nc; ++c) {
                     const int s = c >> 6, l = c & 63;
@@ -785,10 +829,35 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                             const int pos = si.base + (r0 + u) * si.width + l;
                             e[u] = r0 + u < si.height ? Elem{rl.other[pos], rl.score[pos]} : Elem{Q, 0.0f};
                         }
+                        float g[RB];
 #pragma unroll
                         for (int u = 0; u < RB; ++u) {
-                            const float g = prev[e[u].other];
-                            if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e[u].score);
+                            g[u] = prev[e[u].other];
+                            if (g[u] != WFST_NINF) lse_push(acc, (g[u] - c_prev) + e[u].score);
+                        }
+                        if (a != WFST_NINF) {
+                            // posterior of each arc at this visit, as the count kernel forms it
+                            float v[RB];
+                            int nrec = 0;
+#pragma unroll
+                            for (int u = 0; u < RB; ++u) {
+                                v[u] = 0.0f;
+                                if (g[u] != WFST_NINF) v[u] = gb * exp_e((a + e[u].score) + ((g[u] - c_prev) + o));
+                                nrec += v[u] != 0.0f;
+                            }
+                            if (nrec > 0) {
+                                unsigned long long at = atomicAdd(rs.count, (unsigned long long)nrec);
+#pragma unroll
+                                for (int u = 0; u < RB; ++u) {
+                                    if (v[u] == 0.0f) continue;
+                                    if (at < (unsigned long long)rs.cap) {
+                                        const int arc = rl.elem_arc[si.base + (r0 + u) * si.width + l];
+                                        rs.key[at] = ((uint64_t)(uint32_t)arc << 32) | (uint32_t)i;
+                                        rs.val[at] = v[u];
+                                    }
+                                    ++at;
+                                }
+                            }
                         }
                     }
                 }
@@ -813,7 +882,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             }
             float c = unord_f32(s_cmax[t % 3]);
             if (!(c > WFST_NINF)) c = 0.0f;
-            if (tid == 0) C += (double)c;
+            C += (double)c;
             if (t >= 2) {
                 float *tape = beta_slot(tp, bk, bv, b, o0, i - 1);
 #pragma unroll
@@ -834,10 +903,14 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             for (int u = 0; u < TPF; ++u) tk_prev[u] = tk[u];
             li = li_n;
             lf = lf_n;
+            aC = aC_n;
 #pragma unroll
             for (int u = 0; u < RPF; ++u) rk[u] = rk_n[u];
 #pragma unroll
-            for (int u = 0; u < TPF; ++u) tk[u] = tk_n[u];
+            for (int u = 0; u < TPF; ++u) {
+                tk[u] = tk_n[u];
+                ta[u] = ta_n[u];
+            }
         }
         __syncthreads();
     }
@@ -898,18 +971,7 @@ __global__ void visit_table(BatchView bv, TapeView tp, BlockView bk, const int32
             vi.cm = t > 1 ? tp.a_max[i - 1] : 0.0f;
             vi.bm = tp.b_max[i];
             vi.g = grad_log_z ? grad_log_z[b] : 1.0f;
-            vi.a_ptr = nullptr;
-            if (t > 1) {
-                if (bk.c == 0) {
-                    vi.a_ptr = tp.alpha + bv.tok_off[i - 1];
-                } else if (tp.ck_off[i - 1] >= 0) {  // a checkpoint
-                    vi.a_ptr = tp.alpha + tp.ck_off[i - 1];
-                } else {  // recomputed with the visit's block
-                    int blk;
-                    const int64_t r = block_rel(bk, bv, b, o0, i - 1, blk);
-                    vi.a_ptr = bk.abuf[blk & 1] + r;
-                }
-            }
+            vi.a_ptr = t > 1 ? alpha_slot(tp, bk, bv, b, o0, i - 1) : nullptr;
             vi.b_ptr = beta_slot(tp, bk, bv, b, o0, i);
             vi.prev_label = t > 1 ? bv.tokens[i - 1] : -1;
             vi.live = 1;
@@ -1243,6 +1305,20 @@ __global__ void split_group_elems(const LabelInfo *__restrict__ label, const int
     for (int key = blockIdx.x * blockDim.x + threadIdx.x; key < MK; key += gridDim.x * blockDim.x) {
         const bool mine = blk < 0 || K - 1 - key % K == blk;
         out[key] = (mine && n_items_key[key] > 1) ? label[key / K].n_elems : 0;
+    }
+}
+
+// Gradient from the expected-count records sorted by (arc, token position):
+// the first record of each arc sums its run in position order.
+__global__ void record_sums(const uint64_t *__restrict__ key, const float *__restrict__ val, int64_t n,
+                            float *__restrict__ grad)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t arc = (uint32_t)(key[j] >> 32);
+        if (j > 0 && (uint32_t)(key[j - 1] >> 32) == arc) continue;
+        float s = 0.0f;
+        for (int64_t x = j; x < n && (uint32_t)(key[x] >> 32) == arc; ++x) s += val[x];
+        grad[arc] = s;
     }
 }
 

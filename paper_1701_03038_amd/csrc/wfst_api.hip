@@ -91,12 +91,12 @@ enum WsSlot {
     W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
-    W_ILIST, W_ILOFF, W_NUM
+    W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_NUM
 };
 
 // small device counters kept together (one allocation)
 enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_ITEMQ = 3, C_TOTAL = 4 /* int64 at byte 16 */,
-               C_SETOTAL = 6 /* int64 at byte 24 */, C_COUNT = 8 };
+               C_SETOTAL = 6 /* int64 at byte 24 */, C_RECS = 8 /* uint64 at byte 32 */, C_COUNT = 10 };
 
 struct TapeBufs {
     Buf order, tok_off, alpha, a_max, a_log, log_z, tiles, total, ck_size, ck_off, blk_size, blk_base;
@@ -116,6 +116,9 @@ struct wfst_fst {
     int32_t *olabel = nullptr;
     int2 *label_range = nullptr;  // [M] lowest and highest arc id of each label (score updates)
     bool stage_scores = false;    // score updates staged per label through LDS
+    int64_t rec_cap = 0;          // expected-count records per backward call (0: from the batch size)
+    bool rec_fixed = false;       // rec_cap given by the caller (not grown)
+    bool rec_off = false;         // grouped count kernel only
     uint32_t *health = nullptr;  // sticky health bits of the kernels (see wfst_fst_health)
     int64_t bytes = 0;
     int cu_count = 0;
@@ -249,7 +252,7 @@ size_t lds_viterbi(const wfst_fst *f)
 size_t lds_backward(const wfst_fst *f)
 {
     const size_t q1 = (size_t)f->Q + 1;
-    return kSliceCache * sizeof(SliceInfo) + 2 * q1 * sizeof(float) + (q1 + (q1 & 1)) * sizeof(int32_t) +
+    return kSliceCache * sizeof(SliceInfo) + 3 * q1 * sizeof(float) + q1 * sizeof(int32_t) +
            (size_t)backward_list_cap(f) * sizeof(int2);
 }
 size_t lds_lse(const wfst_fst *f, const DevLayout &l)
@@ -443,7 +446,8 @@ int launch_forward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const 
 }
 
 template <int NT>
-int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk)
+int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
+                    const RecordSink &rs)
 {
     const size_t lds = lds_backward(f);
     int grid = 0;
@@ -451,7 +455,7 @@ int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const
     ProfScope prof(f, s, WFST_KERNEL_BACKWARD);
     hipLaunchKernelGGL((backward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start,
                        (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
-                       backward_list_cap(f));
+                       backward_list_cap(f), rs);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -556,12 +560,12 @@ int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, co
     TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(256 * ntiles), s, &tiles));
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(radix_hist, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0, N,
-                           shift, ntiles, hist);
+        hipLaunchKernelGGL(radix_hist<int32_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
+                           N, shift, ntiles, hist);
         ScanSource src;
         src.i64 = hist;
         TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
-        hipLaunchKernelGGL(radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
+        hipLaunchKernelGGL(radix_scatter<int32_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
                            (const int32_t *)v0, N, shift, ntiles, (const int64_t *)hist, k1, v1, f->health);
         std::swap(k0, k1);
         std::swap(v0, v1);
@@ -607,6 +611,43 @@ int final_posteriors(wfst_fst *f, const wfst_tape *tape, const float *grad_log_z
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
+
+// Sort n expected-count records by (arc, token position) and sum each arc's
+// run into grad (arcs without records keep the zero fill).
+int reduce_records(wfst_fst *f, hipStream_t s, int64_t n, int64_t N, uint64_t *k0, float *v0, uint64_t *k1,
+                   float *v1, float *grad)
+{
+    if (n == 0) return WFST_OK;
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    int64_t *hist, *tiles;
+    TRY(ensure_t(f->ws[W_HIST], 256 * ntiles, s, &hist));
+    TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(256 * ntiles), s, &tiles));
+    int pos_bits = 1, arc_bits = 1;
+    while (pos_bits < 32 && ((int64_t)1 << pos_bits) < N) ++pos_bits;
+    while (arc_bits < 32 && ((int64_t)1 << arc_bits) < f->A) ++arc_bits;
+    std::vector<int> shifts;
+    for (int sh = 0; sh < pos_bits; sh += 8) shifts.push_back(sh);
+    for (int sh = 0; sh < arc_bits; sh += 8) shifts.push_back(32 + sh);
+    int32_t *iv0 = reinterpret_cast<int32_t *>(v0), *iv1 = reinterpret_cast<int32_t *>(v1);
+    for (int sh : shifts) {
+        hipLaunchKernelGGL(radix_hist<uint64_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s,
+                           (const uint64_t *)k0, n, sh, ntiles, hist);
+        ScanSource src;
+        src.i64 = hist;
+        TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
+        hipLaunchKernelGGL(radix_scatter<uint64_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s,
+                           (const uint64_t *)k0, (const int32_t *)iv0, n, sh, ntiles, (const int64_t *)hist, k1, iv1,
+                           f->health);
+        std::swap(k0, k1);
+        std::swap(iv0, iv1);
+    }
+    hipLaunchKernelGGL(record_sums, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, (const uint64_t *)k0,
+                       (const float *)reinterpret_cast<float *>(iv0), n, grad);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+constexpr int64_t kRecordsMax = (int64_t)1 << 28;  // records per call before the grouped count kernel is used
 
 }  // namespace
 
@@ -715,6 +756,10 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         f->chunk = L;
         f->nt = nt;
         f->ckpt_mode = opt.checkpoint;
+        if (opt.count_records < -1) return set_err(WFST_EINVAL, "count_records must be >= -1");
+        f->rec_off = opt.count_records == -1;
+        f->rec_fixed = opt.count_records > 0;
+        if (f->rec_fixed) f->rec_cap = opt.count_records;
         if (opt.tape_budget_bytes > 0) f->tape_budget = opt.tape_budget_bytes;
         if (hipGetDevice(&f->device) != hipSuccess) {
             delete f;
@@ -1047,10 +1092,46 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     const BatchView bv = make_view(f, B, N, tape->offsets, tape->tokens, tape->order, tape->tok_off,
                                    counters + C_QUEUE, tape->status);
     int rc;
-    if (bk.c == 0) {
-        DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk)
-        if (rc != WFST_OK) return rc;
+    // Expected counts as records of the backward pass (sorted and summed per
+    // arc) when they fit; otherwise the grouped count kernel below.
+    RecordSink rs;
+    const int64_t rec_cap = std::min(kRecordsMax, f->rec_cap > 0 ? f->rec_cap : 16 * N + 4096);
+    if (f->A > 0 && !f->rec_off) {
+        TRY(ensure_t(f->ws[W_RKEY0], rec_cap, s, &rs.key));
+        TRY(ensure_t(f->ws[W_RVAL0], rec_cap, s, &rs.val));
+        rs.count = reinterpret_cast<unsigned long long *>(counters + C_RECS);
+        rs.cap = rec_cap;
+        rs.grad_log_z = grad_log_z;
     }
+    if (bk.c == 0) {
+        DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk, rs)
+        if (rc != WFST_OK) return rc;
+    } else {
+        for (int32_t k = K - 1; k >= 0; --k) {  // blocks from the end: recompute alpha~, then beta
+            bk.k = k;
+            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
+            DISPATCH_NT(rc, f->nt, launch_forward, f, s, bv, tp, bk, nullptr)
+            if (rc != WFST_OK) return rc;
+            hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
+            DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk, rs)
+            if (rc != WFST_OK) return rc;
+        }
+    }
+    if (rs.key) {
+        unsigned long long n_rec = 0;
+        HIP_OK(hipMemcpyAsync(&n_rec, rs.count, sizeof(n_rec), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if ((int64_t)n_rec <= rec_cap) {
+            ProfScope prof(f, s, WFST_KERNEL_COUNTS);
+            uint64_t *k1;
+            float *v1;
+            TRY(ensure_t(f->ws[W_RKEY1], std::max<int64_t>((int64_t)n_rec, 1), s, &k1));
+            TRY(ensure_t(f->ws[W_RVAL1], std::max<int64_t>((int64_t)n_rec, 1), s, &v1));
+            return reduce_records(f, s, (int64_t)n_rec, N, rs.key, rs.val, k1, v1, grad_arc_score);
+        }
+        if (!f->rec_fixed) f->rec_cap = std::min(kRecordsMax, (int64_t)n_rec + (int64_t)n_rec / 4 + 4096);
+    }
+    RecordSink no_records;
 
     // group the visits (token positions) by (input label, checkpoint block), stable in position
     const int32_t V = 64;
@@ -1134,7 +1215,7 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
             DISPATCH_NT(rc, f->nt, launch_forward, f, s, bv, tp, bk, nullptr)
             if (rc != WFST_OK) return rc;
             hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
-            DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk)
+            DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk, no_records)
             if (rc != WFST_OK) return rc;
             build_visits();
             TRY(counts_block(k));

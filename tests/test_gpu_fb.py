@@ -247,3 +247,33 @@ def test_checkpointing(wf, case):
     assert ck[0].tobytes() == full[0].tobytes(), "log Z differs with checkpointing"
     assert ck[2].tobytes() == full[2].tobytes(), "final posteriors differ with checkpointing"
     assert all(a.tobytes() == b.tobytes() for a, b in zip(ck, auto)), "auto and forced checkpointing differ"
+
+
+@pytest.mark.parametrize("case", ["tiny", "trigram"])
+def test_count_paths(wf, case):
+    """Expected counts by per-visit records (default), by the label-grouped
+    count kernel (count_records=-1), and by the grouped kernel after a record
+    overflow (capacity 1): all within the oracle tolerance; records give the
+    same bits with and without checkpointing; the overflow fallback gives the
+    grouped kernel's bits."""
+    if case == "tiny":
+        fst = synth.tiny_random_fst(11, 6, 3, 30, final_prob=0.7)
+        batch = synth.random_batch(11, fst.num_ilabels, np.random.default_rng(11).integers(0, 30, 80))
+    else:
+        fst, batch = synth.config(3, vocab=2000, batch=200)
+    say(f"case: count paths {case}")
+    olz, opost, ofin, ost = oracle.forward_backward(fst, batch, final_posteriors=True)
+    n_k = visits_per_arc(fst, batch)
+    got = {}
+    for ck in (2, 1):
+        for rec in (0, -1, 1):
+            d = wf.Fst.from_synth(fst, checkpoint=ck, count_records=rec)
+            r = _fb_all(wf, d, batch)
+            r2 = _fb_all(wf, d, batch)
+            np.testing.assert_array_equal(r[3], ost)
+            assert np.all(np.abs(r[1] - opost) <= 1e-5 * np.maximum(1, n_k)), f"ck={ck} rec={rec}"
+            assert r[1].tobytes() == r2[1].tobytes(), f"repeat differs ck={ck} rec={rec}"
+            got[(ck, rec)] = r[1]
+    assert got[(2, 0)].tobytes() == got[(1, 0)].tobytes(), "records differ with checkpointing"
+    assert got[(2, 1)].tobytes() == got[(2, -1)].tobytes(), "overflow fallback differs from the grouped kernel"
+    assert got[(1, 1)].tobytes() == got[(1, -1)].tobytes()
