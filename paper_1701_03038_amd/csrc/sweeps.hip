@@ -596,6 +596,13 @@ constexpr int kSliceCache = 64;  // slice headers of the step's label staged in 
 
 constexpr int rev_key_prefetch(int nt) { return nt >= 1024 ? 3 : nt >= 512 ? 5 : 9; }
 constexpr int kTapeKeyPrefetch = 2;
+// Expected-count records: a step's records are staged in LDS, then copied to a
+// chunk of the record array the workgroup owns; chunks come from one global
+// counter, and a chunk's unused tail is filled with sentinel keys (sorted last,
+// skipped when summing).
+constexpr int kRecStage = 512;
+constexpr int kRecChunk = 256;
+constexpr uint64_t kRecSentinel = ~0ull;
 
 template <int NT>
 __global__ void __launch_bounds__(NT)
@@ -615,10 +622,19 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     int2 *list = reinterpret_cast<int2 *>(aval + (Q + 1));             // [list_cap] {segment, key}
     __shared__ int s_item, s_count;
     __shared__ uint32_t s_cmax[3];
+    __shared__ uint64_t s_rkey[kRecStage];
+    __shared__ float s_rval[kRecStage];
+    __shared__ int s_rn, s_rflush, s_cused, s_csize, s_tailn;
+    __shared__ unsigned long long s_cbase, s_fbase, s_tailb;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const float fmax0 = *final_max;
+    if (tid == 0) {
+        s_rn = 0;
+        s_cbase = 0;
+        s_cused = s_csize = 0;  // no chunk yet
+    }
 
     for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(bv.queue, 1);
@@ -846,14 +862,21 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                                 nrec += v[u] != 0.0f;
                             }
                             if (nrec > 0) {
-                                unsigned long long at = atomicAdd(rs.count, (unsigned long long)nrec);
+                                int at = atomicAdd(&s_rn, nrec);
 #pragma unroll
                                 for (int u = 0; u < RB; ++u) {
                                     if (v[u] == 0.0f) continue;
-                                    if (at < (unsigned long long)rs.cap) {
-                                        const int arc = rl.elem_arc[si.base + (r0 + u) * si.width + l];
-                                        rs.key[at] = ((uint64_t)(uint32_t)arc << 32) | (uint32_t)i;
-                                        rs.val[at] = v[u];
+                                    const int arc = rl.elem_arc[si.base + (r0 + u) * si.width + l];
+                                    const uint64_t key = ((uint64_t)(uint32_t)arc << 32) | (uint32_t)i;
+                                    if (at < kRecStage) {
+                                        s_rkey[at] = key;
+                                        s_rval[at] = v[u];
+                                    } else {  // more than the stage holds: straight to the record array
+                                        const unsigned long long g = atomicAdd(rs.count, 1ull);
+                                        if (g < (unsigned long long)rs.cap) {
+                                            rs.key[g] = key;
+                                            rs.val[g] = v[u];
+                                        }
                                     }
                                     ++at;
                                 }
@@ -868,6 +891,39 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
             block_max_into(my_max, &s_cmax[t % 3], lane);
             __syncthreads();
+            if (rec) {  // copy the step's staged records into the workgroup's chunk
+                if (tid == 0) {
+                    const int n = min(s_rn, kRecStage);
+                    s_rflush = n;
+                    s_tailn = 0;
+                    if (n > 0) {
+                        if (s_cused + n > s_csize) {  // new chunk; the old one's unused tail gets sentinels
+                            s_tailb = s_cbase + s_cused;
+                            s_tailn = s_csize - s_cused;
+                            s_csize = max(kRecChunk, n);
+                            s_cbase = atomicAdd(rs.count, (unsigned long long)s_csize);
+                            s_cused = 0;
+                        }
+                        s_fbase = s_cbase + s_cused;
+                        s_cused += n;
+                    }
+                    s_rn = 0;
+                }
+                __syncthreads();
+                const int n = s_rflush;
+                const unsigned long long base = s_fbase;
+                for (int x = tid; x < n; x += NT) {
+                    const unsigned long long g = base + x;
+                    if (g < (unsigned long long)rs.cap) {
+                        rs.key[g] = s_rkey[x];
+                        rs.val[g] = s_rval[x];
+                    }
+                }
+                for (int x = tid; x < s_tailn; x += NT) {
+                    const unsigned long long g = s_tailb + x;
+                    if (g < (unsigned long long)rs.cap) rs.key[g] = kRecSentinel;
+                }
+            }
             // no thread reads beta~_t any more: clear its support (everything at
             // the first step); the buffer is written again after the next step's
             // first barrier
@@ -914,6 +970,13 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         __syncthreads();
     }
+    // the unused tail of the workgroup's last record chunk
+    __syncthreads();
+    if (rs.key != nullptr)
+        for (int x = s_cused + tid; x < s_csize; x += NT) {
+            const unsigned long long g = s_cbase + x;
+            if (g < (unsigned long long)rs.cap) rs.key[g] = kRecSentinel;
+        }
 }
 
 // =====================================================================
@@ -1315,6 +1378,7 @@ __global__ void record_sums(const uint64_t *__restrict__ key, const float *__res
 {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t arc = (uint32_t)(key[j] >> 32);
+        if (key[j] == kRecSentinel) continue;  // unused record slots sort last
         if (j > 0 && (uint32_t)(key[j - 1] >> 32) == arc) continue;
         float s = 0.0f;
         for (int64_t x = j; x < n && (uint32_t)(key[x] >> 32) == arc; ++x) s += val[x];

@@ -622,9 +622,10 @@ int reduce_records(wfst_fst *f, hipStream_t s, int64_t n, int64_t N, uint64_t *k
     int64_t *hist, *tiles;
     TRY(ensure_t(f->ws[W_HIST], 256 * ntiles, s, &hist));
     TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(256 * ntiles), s, &tiles));
+    // 2^bits > every value, so the all-ones sentinel keys sort after all records
     int pos_bits = 1, arc_bits = 1;
-    while (pos_bits < 32 && ((int64_t)1 << pos_bits) < N) ++pos_bits;
-    while (arc_bits < 32 && ((int64_t)1 << arc_bits) < f->A) ++arc_bits;
+    while (pos_bits < 32 && ((int64_t)1 << pos_bits) <= N) ++pos_bits;
+    while (arc_bits < 32 && ((int64_t)1 << arc_bits) <= f->A) ++arc_bits;
     std::vector<int> shifts;
     for (int sh = 0; sh < pos_bits; sh += 8) shifts.push_back(sh);
     for (int sh = 0; sh < arc_bits; sh += 8) shifts.push_back(32 + sh);
