@@ -103,7 +103,8 @@ __device__ __forceinline__ const float *alpha_slot(const TapeView &tp, const Blo
 struct RecordSink {
     uint64_t *key = nullptr;  // null: no records
     float *val = nullptr;
-    unsigned long long *count = nullptr;
+    unsigned long long *count = nullptr;  // record slots taken (records + unused chunk tails)
+    unsigned long long *total = nullptr;  // records (independent of scheduling)
     int64_t cap = 0;
     const float *grad_log_z = nullptr;  // g_b (null = 1)
 };

@@ -625,7 +625,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     __shared__ uint64_t s_rkey[kRecStage];
     __shared__ float s_rval[kRecStage];
     __shared__ int s_rn, s_rflush, s_cused, s_csize, s_tailn;
-    __shared__ unsigned long long s_cbase, s_fbase, s_tailb;
+    __shared__ unsigned long long s_cbase, s_fbase, s_tailb, s_rtotal;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -633,6 +633,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     if (tid == 0) {
         s_rn = 0;
         s_cbase = 0;
+        s_rtotal = 0;
         s_cused = s_csize = 0;  // no chunk yet
     }
 
@@ -894,6 +895,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             if (rec) {  // copy the step's staged records into the workgroup's chunk
                 if (tid == 0) {
                     const int n = min(s_rn, kRecStage);
+                    s_rtotal += (unsigned long long)s_rn;
                     s_rflush = n;
                     s_tailn = 0;
                     if (n > 0) {
@@ -970,13 +972,15 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         __syncthreads();
     }
-    // the unused tail of the workgroup's last record chunk
+    // the unused tail of the workgroup's last record chunk, and its record count
     __syncthreads();
-    if (rs.key != nullptr)
+    if (rs.key != nullptr) {
         for (int x = s_cused + tid; x < s_csize; x += NT) {
             const unsigned long long g = s_cbase + x;
             if (g < (unsigned long long)rs.cap) rs.key[g] = kRecSentinel;
         }
+        if (tid == 0 && s_rtotal > 0) atomicAdd(rs.total, s_rtotal);
+    }
 }
 
 // =====================================================================

@@ -96,7 +96,8 @@ enum WsSlot {
 
 // small device counters kept together (one allocation)
 enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_ITEMQ = 3, C_TOTAL = 4 /* int64 at byte 16 */,
-               C_SETOTAL = 6 /* int64 at byte 24 */, C_RECS = 8 /* uint64 at byte 32 */, C_COUNT = 10 };
+               C_SETOTAL = 6 /* int64 at byte 24 */, C_RECS = 8 /* uint64 at byte 32 */,
+               C_RTOTAL = 10 /* uint64 at byte 40 */, C_COUNT = 12 };
 
 struct TapeBufs {
     Buf order, tok_off, alpha, a_max, a_log, log_z, tiles, total, ck_size, ck_off, blk_size, blk_base;
@@ -116,8 +117,8 @@ struct wfst_fst {
     int32_t *olabel = nullptr;
     int2 *label_range = nullptr;  // [M] lowest and highest arc id of each label (score updates)
     bool stage_scores = false;    // score updates staged per label through LDS
-    int64_t rec_cap = 0;          // expected-count records per backward call (0: from the batch size)
-    bool rec_fixed = false;       // rec_cap given by the caller (not grown)
+    int64_t rec_cap = 0;          // record slots per backward call (0: from the batch size); grows
+    int64_t rec_max = 0;          // most records a call may use before the grouped count kernel is used
     bool rec_off = false;         // grouped count kernel only
     uint32_t *health = nullptr;  // sticky health bits of the kernels (see wfst_fst_health)
     int64_t bytes = 0;
@@ -759,8 +760,7 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         f->ckpt_mode = opt.checkpoint;
         if (opt.count_records < -1) return set_err(WFST_EINVAL, "count_records must be >= -1");
         f->rec_off = opt.count_records == -1;
-        f->rec_fixed = opt.count_records > 0;
-        if (f->rec_fixed) f->rec_cap = opt.count_records;
+        f->rec_max = opt.count_records > 0 ? opt.count_records : kRecordsMax;
         if (opt.tape_budget_bytes > 0) f->tape_budget = opt.tape_budget_bytes;
         if (hipGetDevice(&f->device) != hipSuccess) {
             delete f;
@@ -1094,44 +1094,65 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
                                    counters + C_QUEUE, tape->status);
     int rc;
     // Expected counts as records of the backward pass (sorted and summed per
-    // arc) when they fit; otherwise the grouped count kernel below.
-    RecordSink rs;
-    const int64_t rec_cap = std::min(kRecordsMax, f->rec_cap > 0 ? f->rec_cap : 16 * N + 4096);
-    if (f->A > 0 && !f->rec_off) {
-        TRY(ensure_t(f->ws[W_RKEY0], rec_cap, s, &rs.key));
-        TRY(ensure_t(f->ws[W_RVAL0], rec_cap, s, &rs.val));
-        rs.count = reinterpret_cast<unsigned long long *>(counters + C_RECS);
-        rs.cap = rec_cap;
-        rs.grad_log_z = grad_log_z;
-    }
-    if (bk.c == 0) {
-        DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk, rs)
-        if (rc != WFST_OK) return rc;
-    } else {
+    // arc) when there are at most rec_max of them; otherwise the grouped count
+    // kernel below.  The choice depends only on the number of records; when
+    // their slots (records plus unused chunk tails) overflow the buffer, the
+    // buffer grows and the pass runs again.
+    auto backward_pass = [&](const RecordSink &sink) -> int {
+        int r = WFST_OK;
+        if (bk.c == 0) {
+            DISPATCH_NT(r, f->nt, launch_backward, f, s, bv, tp, bk, sink)
+            return r;
+        }
         for (int32_t k = K - 1; k >= 0; --k) {  // blocks from the end: recompute alpha~, then beta
             bk.k = k;
             hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
-            DISPATCH_NT(rc, f->nt, launch_forward, f, s, bv, tp, bk, nullptr)
-            if (rc != WFST_OK) return rc;
+            DISPATCH_NT(r, f->nt, launch_forward, f, s, bv, tp, bk, nullptr)
+            if (r != WFST_OK) return r;
             hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
-            DISPATCH_NT(rc, f->nt, launch_backward, f, s, bv, tp, bk, rs)
-            if (rc != WFST_OK) return rc;
+            DISPATCH_NT(r, f->nt, launch_backward, f, s, bv, tp, bk, sink)
+            if (r != WFST_OK) return r;
         }
-    }
-    if (rs.key) {
-        unsigned long long n_rec = 0;
-        HIP_OK(hipMemcpyAsync(&n_rec, rs.count, sizeof(n_rec), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        if ((int64_t)n_rec <= rec_cap) {
-            ProfScope prof(f, s, WFST_KERNEL_COUNTS);
-            uint64_t *k1;
-            float *v1;
-            TRY(ensure_t(f->ws[W_RKEY1], std::max<int64_t>((int64_t)n_rec, 1), s, &k1));
-            TRY(ensure_t(f->ws[W_RVAL1], std::max<int64_t>((int64_t)n_rec, 1), s, &v1));
-            return reduce_records(f, s, (int64_t)n_rec, N, rs.key, rs.val, k1, v1, grad_arc_score);
+        return WFST_OK;
+    };
+    bool beta_done = false;  // the beta tape of the resident-tape pass is written
+    if (f->A > 0 && !f->rec_off) {
+        RecordSink rs;
+        rs.count = reinterpret_cast<unsigned long long *>(counters + C_RECS);
+        rs.total = reinterpret_cast<unsigned long long *>(counters + C_RTOTAL);
+        rs.grad_log_z = grad_log_z;
+        int64_t cap = std::min(kRecordsMax, f->rec_cap > 0 ? f->rec_cap : 16 * N + 4096);
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            TRY(ensure_t(f->ws[W_RKEY0], cap, s, &rs.key));
+            TRY(ensure_t(f->ws[W_RVAL0], cap, s, &rs.val));
+            rs.cap = cap;
+            if (attempt > 0) hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
+            TRY(backward_pass(rs));
+            beta_done = true;
+            unsigned long long got[2] = {0, 0};  // slots, records
+            HIP_OK(hipMemcpyAsync(got, rs.count, sizeof(got), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            if ((int64_t)got[1] > f->rec_max) break;  // too many records: grouped count kernel
+            if ((int64_t)got[0] <= cap) {
+                ProfScope prof(f, s, WFST_KERNEL_COUNTS);
+                uint64_t *k1;
+                float *v1;
+                TRY(ensure_t(f->ws[W_RKEY1], std::max<int64_t>((int64_t)got[0], 1), s, &k1));
+                TRY(ensure_t(f->ws[W_RVAL1], std::max<int64_t>((int64_t)got[0], 1), s, &v1));
+                return reduce_records(f, s, (int64_t)got[0], N, rs.key, rs.val, k1, v1, grad_arc_score);
+            }
+            // slots overflowed: grow to a bound no schedule can pass and run again.  A
+            // chunk holds max(kRecChunk, one step's records <= kRecStage) slots and
+            // is left with a tail under kRecStage; there are at most
+            // records / kRecChunk chunks plus one per workgroup and launch.
+            const int64_t launches = bk.c > 0 ? K : 1;
+            cap = 3 * (int64_t)got[1] + (int64_t)kRecStage * B * launches + 4096;
+            f->rec_cap = std::max<int64_t>(f->rec_cap, std::min(kRecordsMax, (int64_t)got[0] + (int64_t)got[0] / 4));
         }
-        if (!f->rec_fixed) f->rec_cap = std::min(kRecordsMax, (int64_t)n_rec + (int64_t)n_rec / 4 + 4096);
+        // the grouped count kernel needs the beta tape of a pass without records
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
     }
+    if (bk.c == 0 && !beta_done) TRY(backward_pass(RecordSink()));
     RecordSink no_records;
 
     // group the visits (token positions) by (input label, checkpoint block), stable in position
