@@ -604,6 +604,25 @@ constexpr int kRecStage = 512;
 constexpr int kRecChunk = 256;
 constexpr uint64_t kRecSentinel = ~0ull;
 
+// Copy the records placed at the end of the previous step (and sentinels into
+// a chunk tail left behind) from the LDS stage to the record array.
+__device__ __forceinline__ void copy_staged_records(const RecordSink &rs, const uint64_t *stage_key,
+                                                    const float *stage_val, int n, unsigned long long base,
+                                                    int tail_n, unsigned long long tail_base, int tid, int nt)
+{
+    for (int x = tid; x < n; x += nt) {
+        const unsigned long long g = base + x;
+        if (g < (unsigned long long)rs.cap) {
+            rs.key[g] = stage_key[x];
+            rs.val[g] = stage_val[x];
+        }
+    }
+    for (int x = tid; x < tail_n; x += nt) {
+        const unsigned long long g = tail_base + x;
+        if (g < (unsigned long long)rs.cap) rs.key[g] = kRecSentinel;
+    }
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT)
 backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
@@ -634,7 +653,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         s_rn = 0;
         s_cbase = 0;
         s_rtotal = 0;
-        s_cused = s_csize = 0;  // no chunk yet
+        s_rflush = s_tailn = 0;  // nothing staged to copy
+        s_cused = s_csize = 0;   // no chunk yet
     }
 
     for (int pops = 0;; ++pops) {
@@ -705,7 +725,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         LabelInfo lf{};  // forward label of w_{t-1}: the states to compute
         int tk[TPF];
-        float ta[TPF];   // alpha~_{t-1} - c_{t-1} on them (records only)
+        float ta[TPF];   // alpha~_{t-1} on them (records only; normaliser cm subtracted at use)
+        float cm = 0.0f; // c_{t-1}
         double aC = 0.0; // log scale of alpha_{t-1}
 #pragma unroll
         for (int u = 0; u < TPF; ++u) {
@@ -716,14 +737,16 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             const int ip = o0 + t1 - 2;
             lf = fl.label[bv.tokens[ip]];
             const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
-            const float cm = rec ? tp.a_max[ip] : 0.0f;
-            if (rec) aC = tp.a_log[ip];
+            if (rec) {
+                cm = tp.a_max[ip];
+                aC = tp.a_log[ip];
+            }
 #pragma unroll
             for (int u = 0; u < TPF; ++u) {
                 const int j = tid + u * NT;
                 if (j < lf.n_segs) {
                     tk[u] = fl.seg_key[lf.seg_first + j];
-                    if (rec) ta[u] = ap[j] - cm;
+                    if (rec) ta[u] = ap[j];
                 }
             }
         }
@@ -744,12 +767,11 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 for (int u = 0; u < TPF; ++u)
                     if (tk[u] >= 0) {
                         mark[tk[u]] = t;
-                        aval[tk[u]] = ta[u];
+                        aval[tk[u]] = ta[u] - cm;
                     }
                 if (lf.n_segs > TPF * NT) {
                     const int ip = i - 1;
                     const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
-                    const float cm = rec ? tp.a_max[ip] : 0.0f;
                     for (int j = tid + TPF * NT; j < lf.n_segs; j += NT) {
                         const int q = fl.seg_key[lf.seg_first + j];
                         mark[q] = t;
@@ -764,10 +786,12 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             for (int s = tid; s < min(li.n_slices, kSliceCache); s += NT) scache[s] = rl.slice[li.slice_first + s];
             if (tid == 0) s_count = 0;
             __syncthreads();
+            if (rec) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
             // next step's labels and keys, in flight during this step
             LabelInfo li_n{}, lf_n{};
             int rk_n[RPF], tk_n[TPF];
             float ta_n[TPF];
+            float cm_n = 0.0f;
             double aC_n = 0.0;
 #pragma unroll
             for (int u = 0; u < RPF; ++u) rk_n[u] = -1;
@@ -787,14 +811,16 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     const int ip = i - 2;
                     lf_n = fl.label[bv.tokens[ip]];
                     const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
-                    const float cm = rec ? tp.a_max[ip] : 0.0f;
-                    if (rec) aC_n = tp.a_log[ip];
+                    if (rec) {
+                        cm_n = tp.a_max[ip];
+                        aC_n = tp.a_log[ip];
+                    }
 #pragma unroll
                     for (int u = 0; u < TPF; ++u) {
                         const int j = tid + u * NT;
                         if (j < lf_n.n_segs) {
                             tk_n[u] = fl.seg_key[lf_n.seg_first + j];
-                            if (rec) ta_n[u] = ap[j] - cm;
+                            if (rec) ta_n[u] = ap[j];
                         }
                     }
                 }
@@ -892,39 +918,23 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
             block_max_into(my_max, &s_cmax[t % 3], lane);
             __syncthreads();
-            if (rec) {  // copy the step's staged records into the workgroup's chunk
-                if (tid == 0) {
-                    const int n = min(s_rn, kRecStage);
-                    s_rtotal += (unsigned long long)s_rn;
-                    s_rflush = n;
-                    s_tailn = 0;
-                    if (n > 0) {
-                        if (s_cused + n > s_csize) {  // new chunk; the old one's unused tail gets sentinels
-                            s_tailb = s_cbase + s_cused;
-                            s_tailn = s_csize - s_cused;
-                            s_csize = max(kRecChunk, n);
-                            s_cbase = atomicAdd(rs.count, (unsigned long long)s_csize);
-                            s_cused = 0;
-                        }
-                        s_fbase = s_cbase + s_cused;
-                        s_cused += n;
+            if (rec && tid == 0) {  // place the step's staged records in the workgroup's chunk (copied next step)
+                const int n = min(s_rn, kRecStage);
+                s_rtotal += (unsigned long long)s_rn;
+                s_rflush = n;
+                s_tailn = 0;
+                if (n > 0) {
+                    if (s_cused + n > s_csize) {  // new chunk; the old one's unused tail gets sentinels
+                        s_tailb = s_cbase + s_cused;
+                        s_tailn = s_csize - s_cused;
+                        s_csize = max(kRecChunk, n);
+                        s_cbase = atomicAdd(rs.count, (unsigned long long)s_csize);
+                        s_cused = 0;
                     }
-                    s_rn = 0;
+                    s_fbase = s_cbase + s_cused;
+                    s_cused += n;
                 }
-                __syncthreads();
-                const int n = s_rflush;
-                const unsigned long long base = s_fbase;
-                for (int x = tid; x < n; x += NT) {
-                    const unsigned long long g = base + x;
-                    if (g < (unsigned long long)rs.cap) {
-                        rs.key[g] = s_rkey[x];
-                        rs.val[g] = s_rval[x];
-                    }
-                }
-                for (int x = tid; x < s_tailn; x += NT) {
-                    const unsigned long long g = s_tailb + x;
-                    if (g < (unsigned long long)rs.cap) rs.key[g] = kRecSentinel;
-                }
+                s_rn = 0;
             }
             // no thread reads beta~_t any more: clear its support (everything at
             // the first step); the buffer is written again after the next step's
@@ -962,6 +972,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             li = li_n;
             lf = lf_n;
             aC = aC_n;
+            cm = cm_n;
 #pragma unroll
             for (int u = 0; u < RPF; ++u) rk[u] = rk_n[u];
 #pragma unroll
@@ -972,9 +983,11 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         __syncthreads();
     }
-    // the unused tail of the workgroup's last record chunk, and its record count
+    // the records staged by the last step, the unused tail of the last chunk,
+    // and the workgroup's record count
     __syncthreads();
     if (rs.key != nullptr) {
+        copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
         for (int x = s_cused + tid; x < s_csize; x += NT) {
             const unsigned long long g = s_cbase + x;
             if (g < (unsigned long long)rs.cap) rs.key[g] = kRecSentinel;
