@@ -600,7 +600,7 @@ constexpr int kTapeKeyPrefetch = 2;
 // chunk of the record array the workgroup owns; chunks come from one global
 // counter, and a chunk's unused tail is filled with sentinel keys (sorted last,
 // skipped when summing).
-constexpr int kRecStage = 512;
+constexpr int kRecStage = 128;
 constexpr int kRecChunk = 256;
 constexpr uint64_t kRecSentinel = ~0ull;
 
