@@ -277,3 +277,30 @@ def test_count_paths(wf, case):
     assert got[(2, 0)].tobytes() == got[(1, 0)].tobytes(), "records differ with checkpointing"
     assert got[(2, 1)].tobytes() == got[(2, -1)].tobytes(), "overflow fallback differs from the grouped kernel"
     assert got[(1, 1)].tobytes() == got[(1, -1)].tobytes()
+
+
+@pytest.mark.slow
+def test_config3_full(wf):
+    """Training batch of the trigram workload: 172M arcs, 1024 sentences of
+    lognormal length in [5, 60]; log Z, posteriors and final posteriors."""
+    say("case: config3 full: generating")
+    fst, batch = synth.config(3)
+    say("case: config3 full: building device FST")
+    d = wf.Fst.from_synth(fst)
+    say("case: config3 full: forward-backward + oracle")
+    assert_fb_parity(fst, batch, d, "config3 full")
+    assert_final_parity(fst, batch, d, "config3 full")
+
+
+@pytest.mark.slow
+def test_config4_full(wf):
+    """Bigram tagger, 45 tags, vocabulary 200k, 16384 sentences of length
+    U{1..200}: Viterbi bit-exact, forward-backward within tolerance."""
+    from gpu_common import assert_viterbi_parity
+    say("case: config4 full: generating")
+    fst, batch = synth.config(4)
+    d = wf.Fst.from_synth(fst)
+    say("case: config4 full: Viterbi")
+    assert_viterbi_parity(fst, batch, d, "config4 full")
+    say("case: config4 full: forward-backward")
+    assert_fb_parity(fst, batch, d, "config4 full")
