@@ -98,6 +98,58 @@ __device__ __forceinline__ Lse wave_lse(Lse v)
     return v;
 }
 
+// Log-sum-exp with the running max in FP64: terms are alpha^ + theta (exact in
+// FP64), only the shifted exponent and the sum are FP32.  The per-sentence state
+// is kept normalised (the step max subtracted, the scale in FP64), so FP32
+// rounding does not accumulate along a long sentence.
+struct LseD {
+    double m;
+    float s;
+};
+__device__ __forceinline__ void lse_push_d(LseD &acc, double x)
+{
+    const double d = x - acc.m;  // +inf while acc is empty
+    const float e = exp_e((float)(-fabs(d)));
+    if (d > 0.0) {
+        acc.s = acc.s * e + 1.0f;
+        acc.m = x;
+    } else {
+        acc.s = acc.s + e;
+    }
+}
+__device__ __forceinline__ LseD lse_merge_d(LseD a, LseD b)
+{
+    if (b.m == -__builtin_huge_val()) return a;
+    if (a.m == -__builtin_huge_val()) return b;
+    if (b.m > a.m) return LseD{b.m, a.s * exp_e((float)(a.m - b.m)) + b.s};
+    return LseD{a.m, a.s + b.s * exp_e((float)(b.m - a.m))};
+}
+__device__ __forceinline__ double lse_value_d(LseD a)
+{
+    return a.s > 0.0f ? a.m + (double)log_e(a.s) : -__builtin_huge_val();
+}
+__device__ __forceinline__ uint64_t ord_f64(double d)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(d);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unord_f64(uint64_t k)
+{
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+}
+// block max of FP64 values into an LDS cell (ordered uint64); caller syncs
+__device__ __forceinline__ void block_max_d(double v, unsigned long long *cell, int lane)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if (lane == 0) atomicMax(cell, (unsigned long long)ord_f64(v));
+}
+// A segment's value before normalisation, and its key state.
+struct SegVal {
+    double v;
+    int32_t key;
+};
+
 // Rows of a lane's chunk loaded together before they are reduced: enough
 // independent 8-byte loads in flight per wavefront to cover HBM latency.
 // Rows past the slice height read the dead state (index Q, value -inf).
@@ -326,19 +378,18 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 // =====================================================================
 
 // Phase 1 + 2 of one log-semiring step over a sliced layout.  prev holds the
-// previous vector (un-normalised; c_prev is subtracted on the fly), cur
-// receives LSE per segment key.  Returns this thread's max over what it wrote.
-// When tape != nullptr the value of segment j is also stored at tape[j].
+// previous vector normalised (alpha^); the value of every segment j of the
+// label goes to vbuf[j] with its key, unnormalised, in FP64.  Returns this
+// thread's max over what it wrote.
 // A wavefront takes SB of its slices at a time and loads the first RB rows of
 // each before reducing any of them (more loads in flight when chunks are
 // short); a lane reduces its chunk's rows in row order.
 template <int NT, int SB, int RB>
-__device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &li, const float *prev,
-                                          float *cur, float c_prev, Lse *part, float *tape, int lane,
-                                          int wave, int32_t dead)
+__device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &li, const float *prev, LseD *part,
+                                           SegVal *vbuf, int lane, int wave, int32_t dead)
 {
     constexpr int NW = NT / 64;
-    float my_max = WFST_NINF;
+    double my_max = -__builtin_huge_val();
     for (int s0 = wave; s0 < li.n_slices; s0 += NW * SB) {
         SliceInfo si[SB];
 #pragma unroll
@@ -363,11 +414,11 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
             if (lane < si[k].width) {
-                Lse acc{WFST_NINF, 0.0f};
+                LseD acc{-__builtin_huge_val(), 0.0f};
 #pragma unroll
                 for (int u = 0; u < RB; ++u) {
                     const float g = prev[e[k][u].other];
-                    if (g != WFST_NINF) lse_push(acc, (g - c_prev) + e[k][u].score);
+                    if (g != WFST_NINF) lse_push_d(acc, (double)g + (double)e[k][u].score);
                 }
                 for (int r0 = RB; r0 < si[k].height; r0 += RB) {
                     Elem f[RB];
@@ -380,7 +431,7 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
 #pragma unroll
                     for (int u = 0; u < RB; ++u) {
                         const float g = prev[f[u].other];
-                        if (g != WFST_NINF) lse_push(acc, (g - c_prev) + f[u].score);
+                        if (g != WFST_NINF) lse_push_d(acc, (double)g + (double)f[u].score);
                     }
                 }
                 const int c = (s0 + k * NW) * 64 + lane;
@@ -388,11 +439,9 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
                     part[c] = acc;
                 } else {
                     const int j = li.n_multi + (c - li.n_slots);
-                    const int d = dkey[k];
-                    const float v = lse_value(acc);
-                    cur[d] = v;
-                    if (tape) tape[j] = v;
-                    my_max = fmaxf(my_max, v);
+                    const double v = lse_value_d(acc);
+                    vbuf[j] = SegVal{v, dkey[k]};
+                    my_max = fmax(my_max, v);
                 }
             }
         }
@@ -400,24 +449,11 @@ __device__ __forceinline__ float lse_step(const DevLayout &L, const LabelInfo &l
     __syncthreads();
     for (int j = threadIdx.x; j < li.n_multi; j += NT) {
         const SegChunk sc = L.seg_chunk[li.seg_first + j];
-        const int d = L.seg_key[li.seg_first + j];
-        Lse acc = part[sc.first];
-        for (int p = 1; p < sc.count; ++p) {
-            const Lse x = part[sc.first + p];
-            if (x.m == WFST_NINF) continue;
-            if (acc.m == WFST_NINF) {
-                acc = x;
-            } else if (x.m > acc.m) {
-                acc.s = acc.s * exp_e(acc.m - x.m) + x.s;
-                acc.m = x.m;
-            } else {
-                acc.s = acc.s + x.s * exp_e(x.m - acc.m);
-            }
-        }
-        const float v = lse_value(acc);
-        cur[d] = v;
-        if (tape) tape[j] = v;
-        my_max = fmaxf(my_max, v);
+        LseD acc = part[sc.first];
+        for (int p = 1; p < sc.count; ++p) acc = lse_merge_d(acc, part[sc.first + p]);
+        const double v = lse_value_d(acc);
+        vbuf[j] = SegVal{v, L.seg_key[li.seg_first + j]};
+        my_max = fmax(my_max, v);
     }
     return my_max;
 }
@@ -438,10 +474,12 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     extern __shared__ __align__(16) unsigned char smem[];
     float *val0 = reinterpret_cast<float *>(smem);
     float *val1 = val0 + (Q + 1);
-    Lse *part = reinterpret_cast<Lse *>(val1 + (Q + 1));  // 2(Q+1) floats: 8-byte aligned
+    SegVal *vbuf = reinterpret_cast<SegVal *>(val1 + (Q + 1) + ((Q + 1) & 1));  // [max_segs]
+    LseD *part = reinterpret_cast<LseD *>(vbuf + fl.max_segs);                  // [max_slots]
     __shared__ int s_item;
-    __shared__ uint32_t s_cmax[3];
-    __shared__ Lse s_red[NW];
+    __shared__ unsigned long long s_cmax[3];
+    __shared__ double s_rm[NW];
+    __shared__ float s_rs[NW];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -471,7 +509,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                 continue;
             }
             t1 = o1 - o0;
-        } else {  // recompute one block of alpha~ from its checkpoint
+        } else {  // recompute one block of alpha^ from its checkpoint
             if (bv.status[b] != WFST_STATUS_OK) continue;
             o0 = bv.offsets[b];
             o1 = bv.offsets[b + 1];
@@ -484,23 +522,21 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             val0[q] = WFST_NINF;
             val1[q] = WFST_NINF;
         }
-        if (tid < 3) s_cmax[tid] = 0u;
+        if (tid < 3) s_cmax[tid] = 0ull;
         __syncthreads();
-        float c_prev = 0.0f;
         {
             float *first = ((t0 + 1) & 1) ? val0 : val1;
             if (t0 == 0) {
                 if (tid == 0) first[start] = 0.0f;
-            } else {
+            } else {  // the checkpoint holds the normalised state of step t0
                 const int ic = o0 + t0 - 1;
                 const LabelInfo lc = fl.label[bv.tokens[ic]];
                 const float *ta = tp.alpha + tp.ck_off[ic];
                 for (int j = tid; j < lc.n_segs; j += NT) first[fl.seg_key[lc.seg_first + j]] = ta[j];
-                c_prev = tp.a_max[ic];
             }
         }
         __syncthreads();
-        double C = 0.0;  // log scale of alpha (thread 0)
+        double C = 0.0;  // log scale: log alpha_t = alpha^_t + C_t
         LabelInfo li_next = t1 > t0 ? fl.label[bv.tokens[o0 + t0]] : LabelInfo{};
         LabelInfo lp = t0 > 0 ? fl.label[bv.tokens[o0 + t0 - 1]] : LabelInfo{};
         for (int t = t0 + 1; t <= t1; ++t) {
@@ -518,35 +554,39 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             } else {
                 tape = tp.alpha + bv.tok_off[i];
             }
-            const float mx = lse_step<NT, 1, kRowBatch>(fl, li, prev, cur, c_prev, part, tape, lane, wave, Q);
+            const double mx = lse_step<NT, 1, kRowBatch>(fl, li, prev, part, vbuf, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
                 for (int j = tid; j < lp.n_segs; j += NT) prev[fl.seg_key[lp.seg_first + j]] = WFST_NINF;
             }
             lp = li;
-            if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
-            block_max_into(mx, &s_cmax[t % 3], lane);
+            if (tid == 0) s_cmax[(t + 1) % 3] = 0ull;
+            block_max_d(mx, &s_cmax[t % 3], lane);
             __syncthreads();
-            float c = unord_f32(s_cmax[t % 3]);
-            if (!(c > WFST_NINF)) c = 0.0f;
+            double c = unord_f64(s_cmax[t % 3]);
+            if (!(c > -__builtin_huge_val())) c = 0.0;
+            C += c;
+            // normalised state and tape: alpha^_t = alpha_t - c_t
+            for (int j = tid; j < li.n_segs; j += NT) {
+                const SegVal sv = vbuf[j];
+                const float x = sv.v == -__builtin_huge_val() ? WFST_NINF : (float)(sv.v - c);
+                cur[sv.key] = x;
+                if (tape) tape[j] = x;
+            }
             if (tid == 0 && bk.c == 0) {
-                C += (double)c;
-                tp.a_max[i] = c;
+                tp.a_max[i] = 0.0f;  // the tape is already normalised
                 tp.a_log[i] = C;
             }
-            c_prev = c;
-        }
-        if (bk.c > 0) {
             __syncthreads();
-            continue;
         }
+        if (bk.c > 0) continue;
         // log Z = C_T + LSE_q(alpha^_T[q] + f[q])
-        Lse acc{WFST_NINF, 0.0f};
+        LseD acc{-__builtin_huge_val(), 0.0f};
         if (T == 0) {
             if (tid == 0) {
                 const float f = final_score[start];
-                if (f != WFST_NINF) acc = Lse{f, 1.0f};
+                if (f != WFST_NINF) acc = LseD{(double)f, 1.0f};
             }
         } else {
             const float *fin = (T & 1) ? val1 : val0;
@@ -555,22 +595,26 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                 const int d = fl.seg_key[li.seg_first + j];
                 const float x = fin[d], f = final_score[d];
                 if (x == WFST_NINF || f == WFST_NINF) continue;
-                lse_push(acc, (x - c_prev) + f);
+                lse_push_d(acc, (double)x + (double)f);
             }
         }
-        acc = wave_lse(acc);
-        if (lane == 0) s_red[wave] = acc;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc = lse_merge_d(acc, LseD{__shfl_xor(acc.m, o, 64), __shfl_xor(acc.s, o, 64)});
+        if (lane == 0) {
+            s_rm[wave] = acc.m;
+            s_rs[wave] = acc.s;
+        }
         __syncthreads();
         if (tid == 0) {
-            Lse tot = s_red[0];
-            for (int w = 1; w < NW; ++w) tot = lse_merge(tot, s_red[w]);
-            const float lz32 = lse_value(tot);
-            if (lz32 == WFST_NINF) {
+            LseD tot{s_rm[0], s_rs[0]};
+            for (int w = 1; w < NW; ++w) tot = lse_merge_d(tot, LseD{s_rm[w], s_rs[w]});
+            const double lzr = lse_value_d(tot);
+            if (lzr == -__builtin_huge_val()) {
                 bv.status[b] = WFST_STATUS_NO_PATH;
                 log_z_out[b] = WFST_NINF;
                 tp.log_z[b] = -__builtin_huge_val();
             } else {
-                const double lz = C + (double)lz32;
+                const double lz = C + lzr;
                 bv.status[b] = WFST_STATUS_OK;
                 log_z_out[b] = (float)lz;
                 tp.log_z[b] = lz;
@@ -592,7 +636,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 // sweep computes; only the per-step normaliser (the max over the computed
 // states) is taken over fewer states.  The next step's labels and segment keys
 // are loaded while the current step runs.
-constexpr int kSliceCache = 64;  // slice headers of the step's label staged in LDS
+constexpr int kSliceCache = 32;  // slice headers of the step's label staged in LDS
 
 constexpr int rev_key_prefetch(int nt) { return nt >= 1024 ? 3 : nt >= 512 ? 5 : 9; }
 constexpr int kTapeKeyPrefetch = 2;
@@ -600,7 +644,7 @@ constexpr int kTapeKeyPrefetch = 2;
 // chunk of the record array the workgroup owns; chunks come from one global
 // counter, and a chunk's unused tail is filled with sentinel keys (sorted last,
 // skipped when summing).
-constexpr int kRecStage = 128;
+constexpr int kRecStage = 64;
 constexpr int kRecChunk = 256;
 constexpr uint64_t kRecSentinel = ~0ull;
 
@@ -639,8 +683,9 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     int32_t *mark = reinterpret_cast<int32_t *>(val1 + (Q + 1));       // [Q+1] step stamp of states to compute
     float *aval = reinterpret_cast<float *>(mark + (Q + 1));           // [Q+1] alpha~_{t-1} - c_{t-1} there
     int2 *list = reinterpret_cast<int2 *>(aval + (Q + 1));             // [list_cap] {segment, key}
+    double *lval = reinterpret_cast<double *>(list + list_cap);        // [list_cap] unnormalised value
     __shared__ int s_item, s_count;
-    __shared__ uint32_t s_cmax[3];
+    __shared__ unsigned long long s_cmax[3];
     __shared__ uint64_t s_rkey[kRecStage];
     __shared__ float s_rval[kRecStage];
     __shared__ int s_rn, s_rflush, s_cused, s_csize, s_tailn;
@@ -683,31 +728,29 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         float *vT = (t1 & 1) ? val1 : val0;
         float *vO = (t1 & 1) ? val0 : val1;
-        for (int q = tid; q <= Q; q += NT) {
-            vT[q] = (t1 == T && q < Q) ? final_score[q] : WFST_NINF;
+        for (int q = tid; q <= Q; q += NT) {  // beta^_T = f - max f, with C = max f
+            const float f = q < Q ? final_score[q] : WFST_NINF;
+            vT[q] = (t1 == T && f != WFST_NINF) ? f - fmax0 : WFST_NINF;
             vO[q] = WFST_NINF;
             mark[q] = -1;
         }
         __syncthreads();
-        float c_prev;
-        double C;
+        double C;  // log scale: log beta_t = beta^_t + C_t
         if (t1 == T) {
-            // beta_T on the destinations of w_T, for the expected counts
+            // beta^_T on the destinations of w_T, for the expected counts
             const LabelInfo lf = fl.label[bv.tokens[o1 - 1]];
             float *tape = beta_slot(tp, bk, bv, b, o0, o1 - 1);
             for (int j = tid; j < lf.n_segs; j += NT) tape[j] = vT[fl.seg_key[lf.seg_first + j]];
             if (tid == 0) {
-                tp.b_max[o1 - 1] = fmax0;
+                tp.b_max[o1 - 1] = 0.0f;
                 tp.b_log[o1 - 1] = (double)fmax0;
             }
-            c_prev = fmax0;
             C = (double)fmax0;
-        } else {  // resume from beta~_{t1} kept by the previous (later) block
+        } else {  // resume from beta^_{t1} kept by the previous (later) block
             const int i1 = o0 + t1 - 1;
             const LabelInfo lf = fl.label[bv.tokens[i1]];
             const float *tape = beta_slot(tp, bk, bv, b, o0, i1);
             for (int j = tid; j < lf.n_segs; j += NT) vT[fl.seg_key[lf.seg_first + j]] = tape[j];
-            c_prev = tp.b_max[i1];
             C = tp.b_log[i1];
         }
         if (tid < 3) s_cmax[tid] = 0u;
@@ -787,6 +830,14 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             if (tid == 0) s_count = 0;
             __syncthreads();
             if (rec) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
+            if (t < t1) {  // tape of beta^_t (this step's input), normalised at the end of step t+1
+                float *tape = beta_slot(tp, bk, bv, b, o0, i);
+#pragma unroll
+                for (int u = 0; u < TPF; ++u)
+                    if (tk_prev[u] >= 0) tape[tid + u * NT] = prev[tk_prev[u]];
+                for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
+                    tape[j] = prev[fl.seg_key[lf_prev.seg_first + j]];
+            }
             // next step's labels and keys, in flight during this step
             LabelInfo li_n{}, lf_n{};
             int rk_n[RPF], tk_n[TPF];
@@ -847,7 +898,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 n = list_cap;
             }
             // C: one thread per marked segment, its chunks and rows in layout order
-            float my_max = WFST_NINF;
+            double my_max = -__builtin_huge_val();
             for (int x = tid; x < n; x += NT) {
                 const int2 jk = list[x];
                 const int j = jk.x;
@@ -860,8 +911,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     c0 = li.n_slots + (j - li.n_multi);
                     nc = 1;
                 }
-                const float a = rec ? aval[jk.y] : WFST_NINF;  // alpha~_{t-1} - c_{t-1} at the source
-                Lse acc{WFST_NINF, 0.0f};
+                const float a = rec ? aval[jk.y] : WFST_NINF;  // alpha^_{t-1} at the source
+                LseD acc{-__builtin_huge_val(), 0.0f};
                 for (int c = c0; c < c0 + nc; ++c) {
                     const int s = c >> 6, l = c & 63;
                     const SliceInfo si = s < kSliceCache ? scache[s] : rl.slice[li.slice_first + s];
@@ -876,7 +927,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
 #pragma unroll
                         for (int u = 0; u < RB; ++u) {
                             g[u] = prev[e[u].other];
-                            if (g[u] != WFST_NINF) lse_push(acc, (g[u] - c_prev) + e[u].score);
+                            if (g[u] != WFST_NINF) lse_push_d(acc, (double)g[u] + (double)e[u].score);
                         }
                         if (a != WFST_NINF) {
                             // posterior of each arc at this visit, as the count kernel forms it
@@ -885,7 +936,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
 #pragma unroll
                             for (int u = 0; u < RB; ++u) {
                                 v[u] = 0.0f;
-                                if (g[u] != WFST_NINF) v[u] = gb * exp_e((a + e[u].score) + ((g[u] - c_prev) + o));
+                                if (g[u] != WFST_NINF) v[u] = gb * exp_e((a + e[u].score) + (g[u] + o));
                                 nrec += v[u] != 0.0f;
                             }
                             if (nrec > 0) {
@@ -911,13 +962,23 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                         }
                     }
                 }
-                const float v = lse_value(acc);
-                cur[jk.y] = v;
-                my_max = fmaxf(my_max, v);
+                const double v = lse_value_d(acc);
+                lval[x] = v;
+                my_max = fmax(my_max, v);
             }
-            if (tid == 0) s_cmax[(t + 1) % 3] = 0u;
-            block_max_into(my_max, &s_cmax[t % 3], lane);
+            if (tid == 0) s_cmax[(t + 1) % 3] = 0ull;
+            block_max_d(my_max, &s_cmax[t % 3], lane);
             __syncthreads();
+            double c = unord_f64(s_cmax[t % 3]);
+            if (!(c > -__builtin_huge_val())) c = 0.0;
+            // beta^_{t-1} = beta_{t-1} - c (read by the next step after its first barrier)
+            for (int x = tid; x < n; x += NT) {
+                const double v = lval[x];
+                cur[list[x].y] = v == -__builtin_huge_val() ? WFST_NINF : (float)(v - c);
+                if (t == 1 && list[x].y == start)
+                    tp.log_z_bwd[b] = v == -__builtin_huge_val() ? -__builtin_huge_val() : C + v;
+            }
+            C += c;
             if (rec && tid == 0) {  // place the step's staged records in the workgroup's chunk (copied next step)
                 const int n = min(s_rn, kRecStage);
                 s_rtotal += (unsigned long long)s_rn;
@@ -948,24 +1009,10 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
                     prev[fl.seg_key[lf_prev.seg_first + j]] = WFST_NINF;
             }
-            float c = unord_f32(s_cmax[t % 3]);
-            if (!(c > WFST_NINF)) c = 0.0f;
-            C += (double)c;
-            if (t >= 2) {
-                float *tape = beta_slot(tp, bk, bv, b, o0, i - 1);
-#pragma unroll
-                for (int u = 0; u < TPF; ++u)
-                    if (tk[u] >= 0) tape[tid + u * NT] = cur[tk[u]];
-                for (int j = tid + TPF * NT; j < lf.n_segs; j += NT) tape[j] = cur[fl.seg_key[lf.seg_first + j]];
-                if (tid == 0) {
-                    tp.b_max[i - 1] = c;
-                    tp.b_log[i - 1] = C;
-                }
-            } else if (tid == 0) {
-                const float x = cur[start];
-                tp.log_z_bwd[b] = x == WFST_NINF ? -__builtin_huge_val() : C + (double)(x - c);
+            if (t >= 2 && tid == 0) {
+                tp.b_max[i - 1] = 0.0f;  // the tape is normalised
+                tp.b_log[i - 1] = C;
             }
-            c_prev = c;
             lf_prev = lf;
 #pragma unroll
             for (int u = 0; u < TPF; ++u) tk_prev[u] = tk[u];
@@ -980,6 +1027,15 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 tk[u] = tk_n[u];
                 ta[u] = ta_n[u];
             }
+        }
+        __syncthreads();
+        if (t0 >= 1) {  // tape of beta^_{t0}, the last step's output (a block boundary)
+            float *fin = ((t0 + 1) & 1) ? val0 : val1;
+            float *tape = beta_slot(tp, bk, bv, b, o0, o0 + t0 - 1);
+#pragma unroll
+            for (int u = 0; u < TPF; ++u)
+                if (tk_prev[u] >= 0) tape[tid + u * NT] = fin[tk_prev[u]];
+            for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT) tape[j] = fin[fl.seg_key[lf_prev.seg_first + j]];
         }
         __syncthreads();
     }

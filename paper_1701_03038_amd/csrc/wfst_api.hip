@@ -254,11 +254,13 @@ size_t lds_backward(const wfst_fst *f)
 {
     const size_t q1 = (size_t)f->Q + 1;
     return kSliceCache * sizeof(SliceInfo) + 3 * q1 * sizeof(float) + q1 * sizeof(int32_t) +
-           (size_t)backward_list_cap(f) * sizeof(int2);
+           (size_t)backward_list_cap(f) * (sizeof(int2) + sizeof(double));
 }
 size_t lds_lse(const wfst_fst *f, const DevLayout &l)
 {
-    return (size_t)(f->Q + 1) * 2 * sizeof(float) + (size_t)std::max(l.max_slots, 1) * sizeof(Lse);
+    const size_t q1 = (size_t)f->Q + 1;
+    return (2 * q1 + (q1 & 1)) * sizeof(float) + (size_t)std::max(l.max_segs, 1) * sizeof(SegVal) +
+           (size_t)std::max(l.max_slots, 1) * sizeof(LseD);
 }
 size_t lds_counts(const wfst_fst *f)
 {
