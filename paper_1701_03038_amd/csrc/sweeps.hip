@@ -144,6 +144,27 @@ __device__ __forceinline__ void block_max_d(double v, unsigned long long *cell, 
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     if (lane == 0) atomicMax(cell, (unsigned long long)ord_f64(v));
 }
+// Fold a batch of terms (-inf = none) into acc: the batch max by a pairwise
+// tree, the shifted exponentials independent of each other, one merge; the
+// dependency chain is a few FP64 ops per batch instead of per term.
+template <int RB>
+__device__ __forceinline__ void lse_push_batch(LseD &acc, const double (&x)[RB])
+{
+    double t[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) t[u] = x[u];
+#pragma unroll
+    for (int w = RB / 2; w >= 1; w /= 2)
+#pragma unroll
+        for (int u = 0; u < w; ++u) t[u] = fmax(t[u], t[u + w]);
+    const double m = t[0];
+    if (m == -__builtin_huge_val()) return;
+    float sum = 0.0f;
+#pragma unroll
+    for (int u = 0; u < RB; ++u) sum += exp_e((float)(x[u] - m));
+    acc = lse_merge_d(acc, LseD{m, sum});
+}
+
 // A segment's value before normalisation, and its key state.
 struct SegVal {
     double v;
@@ -415,10 +436,11 @@ __device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &
         for (int k = 0; k < SB; ++k) {
             if (lane < si[k].width) {
                 LseD acc{-__builtin_huge_val(), 0.0f};
+                {
+                    double x[RB];
 #pragma unroll
-                for (int u = 0; u < RB; ++u) {
-                    const float g = prev[e[k][u].other];
-                    if (g != WFST_NINF) lse_push_d(acc, (double)g + (double)e[k][u].score);
+                    for (int u = 0; u < RB; ++u) x[u] = (double)prev[e[k][u].other] + (double)e[k][u].score;
+                    lse_push_batch<RB>(acc, x);
                 }
                 for (int r0 = RB; r0 < si[k].height; r0 += RB) {
                     Elem f[RB];
@@ -428,11 +450,10 @@ __device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &
                                    ? Elem{L.other[si[k].base + (r0 + u) * si[k].width + lane],
                                           L.score[si[k].base + (r0 + u) * si[k].width + lane]}
                                    : Elem{dead, 0.0f};
+                    double x[RB];
 #pragma unroll
-                    for (int u = 0; u < RB; ++u) {
-                        const float g = prev[f[u].other];
-                        if (g != WFST_NINF) lse_push_d(acc, (double)g + (double)f[u].score);
-                    }
+                    for (int u = 0; u < RB; ++u) x[u] = (double)prev[f[u].other] + (double)f[u].score;
+                    lse_push_batch<RB>(acc, x);
                 }
                 const int c = (s0 + k * NW) * 64 + lane;
                 if (c < li.n_slots) {
@@ -924,11 +945,13 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                             e[u] = r0 + u < si.height ? Elem{rl.other[pos], rl.score[pos]} : Elem{Q, 0.0f};
                         }
                         float g[RB];
+                        double x[RB];
 #pragma unroll
                         for (int u = 0; u < RB; ++u) {
                             g[u] = prev[e[u].other];
-                            if (g[u] != WFST_NINF) lse_push_d(acc, (double)g[u] + (double)e[u].score);
+                            x[u] = (double)g[u] + (double)e[u].score;
                         }
+                        lse_push_batch<RB>(acc, x);
                         if (a != WFST_NINF) {
                             // posterior of each arc at this visit, as the count kernel forms it
                             float v[RB];
