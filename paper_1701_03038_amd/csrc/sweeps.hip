@@ -575,7 +575,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             } else {
                 tape = tp.alpha + bv.tok_off[i];
             }
-            const double mx = lse_step<NT, 1, kRowBatch>(fl, li, prev, part, vbuf, lane, wave, Q);
+            const double mx = lse_step<NT, 2, 8>(fl, li, prev, part, vbuf, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
@@ -696,7 +696,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
 {
     constexpr int RPF = rev_key_prefetch(NT);
     constexpr int TPF = kTapeKeyPrefetch;
-    constexpr int RB = 8;
+    constexpr int RB = 4;
     extern __shared__ __align__(16) unsigned char smem[];
     SliceInfo *scache = reinterpret_cast<SliceInfo *>(smem);           // [kSliceCache]
     float *val0 = reinterpret_cast<float *>(scache + kSliceCache);     // [Q+1]
