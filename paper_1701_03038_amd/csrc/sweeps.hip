@@ -406,8 +406,8 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 // each before reducing any of them (more loads in flight when chunks are
 // short); a lane reduces its chunk's rows in row order.
 template <int NT, int SB, int RB>
-__device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &li, const float *prev, LseD *part,
-                                           SegVal *vbuf, int lane, int wave, int32_t dead)
+__device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &li, const float *prev, double *part,
+                                           double *vval, int32_t *vkey, int lane, int wave, int32_t dead)
 {
     constexpr int NW = NT / 64;
     double my_max = -__builtin_huge_val();
@@ -456,12 +456,13 @@ __device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &
                     lse_push_batch<RB>(acc, x);
                 }
                 const int c = (s0 + k * NW) * 64 + lane;
+                const double v = lse_value_d(acc);
                 if (c < li.n_slots) {
-                    part[c] = acc;
+                    part[c] = v;  // a chunk of a multi-chunk segment, in log form
                 } else {
                     const int j = li.n_multi + (c - li.n_slots);
-                    const double v = lse_value_d(acc);
-                    vbuf[j] = SegVal{v, dkey[k]};
+                    vval[j] = v;
+                    vkey[j] = dkey[k];
                     my_max = fmax(my_max, v);
                 }
             }
@@ -470,10 +471,14 @@ __device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &
     __syncthreads();
     for (int j = threadIdx.x; j < li.n_multi; j += NT) {
         const SegChunk sc = L.seg_chunk[li.seg_first + j];
-        LseD acc = part[sc.first];
-        for (int p = 1; p < sc.count; ++p) acc = lse_merge_d(acc, part[sc.first + p]);
+        LseD acc{-__builtin_huge_val(), 0.0f};
+        for (int p = 0; p < sc.count; ++p) {  // chunks in order
+            const double x = part[sc.first + p];
+            if (x != -__builtin_huge_val()) lse_push_d(acc, x);
+        }
         const double v = lse_value_d(acc);
-        vbuf[j] = SegVal{v, L.seg_key[li.seg_first + j]};
+        vval[j] = v;
+        vkey[j] = L.seg_key[li.seg_first + j];
         my_max = fmax(my_max, v);
     }
     return my_max;
@@ -495,8 +500,9 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     extern __shared__ __align__(16) unsigned char smem[];
     float *val0 = reinterpret_cast<float *>(smem);
     float *val1 = val0 + (Q + 1);
-    SegVal *vbuf = reinterpret_cast<SegVal *>(val1 + (Q + 1) + ((Q + 1) & 1));  // [max_segs]
-    LseD *part = reinterpret_cast<LseD *>(vbuf + fl.max_segs);                  // [max_slots]
+    double *vval = reinterpret_cast<double *>(val1 + (Q + 1) + ((Q + 1) & 1));  // [max_segs] step values
+    double *part = vval + fl.max_segs;                                          // [max_slots] chunk values
+    int32_t *vkey = reinterpret_cast<int32_t *>(part + max(fl.max_slots, 1));   // [max_segs] their keys
     __shared__ int s_item;
     __shared__ unsigned long long s_cmax[3];
     __shared__ double s_rm[NW];
@@ -575,7 +581,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             } else {
                 tape = tp.alpha + bv.tok_off[i];
             }
-            const double mx = lse_step<NT, 2, 8>(fl, li, prev, part, vbuf, lane, wave, Q);
+            const double mx = lse_step<NT, 2, 8>(fl, li, prev, part, vval, vkey, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
@@ -590,9 +596,9 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             C += c;
             // normalised state and tape: alpha^_t = alpha_t - c_t
             for (int j = tid; j < li.n_segs; j += NT) {
-                const SegVal sv = vbuf[j];
-                const float x = sv.v == -__builtin_huge_val() ? WFST_NINF : (float)(sv.v - c);
-                cur[sv.key] = x;
+                const double v = vval[j];
+                const float x = v == -__builtin_huge_val() ? WFST_NINF : (float)(v - c);
+                cur[vkey[j]] = x;
                 if (tape) tape[j] = x;
             }
             if (tid == 0 && bk.c == 0) {

@@ -259,8 +259,8 @@ size_t lds_backward(const wfst_fst *f)
 size_t lds_lse(const wfst_fst *f, const DevLayout &l)
 {
     const size_t q1 = (size_t)f->Q + 1;
-    return (2 * q1 + (q1 & 1)) * sizeof(float) + (size_t)std::max(l.max_segs, 1) * sizeof(SegVal) +
-           (size_t)std::max(l.max_slots, 1) * sizeof(LseD);
+    return (2 * q1 + (q1 & 1)) * sizeof(float) + (size_t)std::max(l.max_segs, 1) * (sizeof(double) + sizeof(int32_t)) +
+           (size_t)std::max(l.max_slots, 1) * sizeof(double);
 }
 size_t lds_counts(const wfst_fst *f)
 {
