@@ -165,6 +165,29 @@ __device__ __forceinline__ void lse_push_batch(LseD &acc, const double (&x)[RB])
     acc = lse_merge_d(acc, LseD{m, sum});
 }
 
+// The same for terms g[u] + e[u].score formed in FP64 on the fly (no FP64
+// copy of the batch: the first tree level is built from the FP32 operands and
+// each term is re-formed for its exponential).
+template <int RB>
+__device__ __forceinline__ void lse_push_terms(LseD &acc, const float (&g)[RB], const Elem (&e)[RB])
+{
+    static_assert(RB >= 2 && (RB & (RB - 1)) == 0, "row batch must be a power of two");
+    double t[RB / 2];
+#pragma unroll
+    for (int u = 0; u < RB / 2; ++u)
+        t[u] = fmax((double)g[u] + (double)e[u].score, (double)g[u + RB / 2] + (double)e[u + RB / 2].score);
+#pragma unroll
+    for (int w = RB / 4; w >= 1; w /= 2)
+#pragma unroll
+        for (int u = 0; u < w; ++u) t[u] = fmax(t[u], t[u + w]);
+    const double m = t[0];
+    if (m == -__builtin_huge_val()) return;
+    float sum = 0.0f;
+#pragma unroll
+    for (int u = 0; u < RB; ++u) sum += exp_e((float)(((double)g[u] + (double)e[u].score) - m));
+    acc = lse_merge_d(acc, LseD{m, sum});
+}
+
 // A segment's value before normalisation, and its key state.
 struct SegVal {
     double v;
@@ -437,10 +460,10 @@ __device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &
             if (lane < si[k].width) {
                 LseD acc{-__builtin_huge_val(), 0.0f};
                 {
-                    double x[RB];
+                    float g[RB];
 #pragma unroll
-                    for (int u = 0; u < RB; ++u) x[u] = (double)prev[e[k][u].other] + (double)e[k][u].score;
-                    lse_push_batch<RB>(acc, x);
+                    for (int u = 0; u < RB; ++u) g[u] = prev[e[k][u].other];
+                    lse_push_terms<RB>(acc, g, e[k]);
                 }
                 for (int r0 = RB; r0 < si[k].height; r0 += RB) {
                     Elem f[RB];
@@ -450,10 +473,10 @@ __device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &
                                    ? Elem{L.other[si[k].base + (r0 + u) * si[k].width + lane],
                                           L.score[si[k].base + (r0 + u) * si[k].width + lane]}
                                    : Elem{dead, 0.0f};
-                    double x[RB];
+                    float g[RB];
 #pragma unroll
-                    for (int u = 0; u < RB; ++u) x[u] = (double)prev[f[u].other] + (double)f[u].score;
-                    lse_push_batch<RB>(acc, x);
+                    for (int u = 0; u < RB; ++u) g[u] = prev[f[u].other];
+                    lse_push_terms<RB>(acc, g, f);
                 }
                 const int c = (s0 + k * NW) * 64 + lane;
                 const double v = lse_value_d(acc);
@@ -581,7 +604,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             } else {
                 tape = tp.alpha + bv.tok_off[i];
             }
-            const double mx = lse_step<NT, 2, 8>(fl, li, prev, part, vval, vkey, lane, wave, Q);
+            const double mx = lse_step<NT, 1, kRowBatch>(fl, li, prev, part, vval, vkey, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
@@ -951,13 +974,9 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                             e[u] = r0 + u < si.height ? Elem{rl.other[pos], rl.score[pos]} : Elem{Q, 0.0f};
                         }
                         float g[RB];
-                        double x[RB];
 #pragma unroll
-                        for (int u = 0; u < RB; ++u) {
-                            g[u] = prev[e[u].other];
-                            x[u] = (double)g[u] + (double)e[u].score;
-                        }
-                        lse_push_batch<RB>(acc, x);
+                        for (int u = 0; u < RB; ++u) g[u] = prev[e[u].other];
+                        lse_push_terms<RB>(acc, g, e);
                         if (a != WFST_NINF) {
                             // posterior of each arc at this visit, as the count kernel forms it
                             float v[RB];
