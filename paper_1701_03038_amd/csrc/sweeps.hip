@@ -188,6 +188,22 @@ __device__ __forceinline__ void lse_push_terms(LseD &acc, const float (&g)[RB], 
     acc = lse_merge_d(acc, LseD{m, sum});
 }
 
+// Move a label header loaded ahead into scalar registers where this is cheap
+// (its load long done), so that a later wait on vector memory -- which also
+// counts the stores issued in between -- is not needed for it.
+__device__ __forceinline__ LabelInfo uniform_label(LabelInfo l)
+{
+    l.slice_first = wave_uniform(l.slice_first);
+    l.n_slices = wave_uniform(l.n_slices);
+    l.seg_first = wave_uniform(l.seg_first);
+    l.n_segs = wave_uniform(l.n_segs);
+    l.n_multi = wave_uniform(l.n_multi);
+    l.n_slots = wave_uniform(l.n_slots);
+    l.elem_first = wave_uniform(l.elem_first);
+    l.n_elems = wave_uniform(l.n_elems);
+    return l;
+}
+
 // A segment's value before normalisation, and its key state.
 struct SegVal {
     double v;
@@ -258,7 +274,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(bv.queue, 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = wave_uniform(s_item);  // uniform: the sentence's loads go through the scalar unit
         __syncthreads();
         if (item >= bv.B) break;
         if (item < 0 || pops > bv.B) {
@@ -538,7 +554,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(bv.queue, 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = wave_uniform(s_item);  // uniform: the sentence's loads go through the scalar unit
         __syncthreads();
         if (item >= bv.B) break;
         if (item < 0 || pops > bv.B) {
@@ -617,6 +633,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             double c = unord_f64(s_cmax[t % 3]);
             if (!(c > -__builtin_huge_val())) c = 0.0;
             C += c;
+            li_next = uniform_label(li_next);  // before the tape stores below
             // normalised state and tape: alpha^_t = alpha_t - c_t
             for (int j = tid; j < li.n_segs; j += NT) {
                 const double v = vval[j];
@@ -755,7 +772,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(bv.queue, 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = wave_uniform(s_item);  // uniform: the sentence's loads go through the scalar unit
         __syncthreads();
         if (item >= bv.B) break;
         if (item < 0 || pops > bv.B) {
@@ -1269,7 +1286,7 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
     for (int pops = 0;; ++pops) {
         if (tid == 0) s_item = atomicAdd(item_queue, 1);
         __syncthreads();
-        const int idx = s_item;
+        const int idx = wave_uniform(s_item);
         __syncthreads();
         if (idx >= nit) break;
         if (idx < 0 || pops > nit) {
