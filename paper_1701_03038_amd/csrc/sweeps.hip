@@ -219,8 +219,12 @@ __device__ __forceinline__ void load_rows(const int32_t *op, const float *sp, in
                                           int32_t dead, Elem (&e)[kRowBatch])
 {
 #pragma unroll
-    for (int u = 0; u < kRowBatch; ++u)
-        e[u] = r0 + u < height ? Elem{op[(r0 + u) * width], sp[(r0 + u) * width]} : Elem{dead, 0.0f};
+    for (int u = 0; u < kRowBatch; ++u) {  // no branches: rows past the height re-read the last row
+        const int at = min(r0 + u, height - 1) * width;
+        const int32_t o = op[at];
+        const float sc = sp[at];
+        e[u] = r0 + u < height ? Elem{o, sc} : Elem{dead, 0.0f};
+    }
 }
 
 // Validates the sentence's offsets and tokens; returns a WFST_STATUS_* code.
@@ -441,69 +445,47 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 // previous vector normalised (alpha^); the value of every segment j of the
 // label goes to vbuf[j] with its key, unnormalised, in FP64.  Returns this
 // thread's max over what it wrote.
-// A wavefront takes SB of its slices at a time and loads the first RB rows of
-// each before reducing any of them (more loads in flight when chunks are
-// short); a lane reduces its chunk's rows in row order.
-template <int NT, int SB, int RB>
+// A lane reduces its chunk's rows in row order, RB rows at a time.  The rows
+// of a batch are loaded without branches (rows past the slice's height re-read
+// its last row and are then replaced by a dead element), so that all RB loads
+// are in flight together.
+template <int NT, int RB>
 __device__ __forceinline__ double lse_step(const DevLayout &L, const LabelInfo &li, const float *prev, double *part,
                                            double *vval, int32_t *vkey, int lane, int wave, int32_t dead)
 {
     constexpr int NW = NT / 64;
     double my_max = -__builtin_huge_val();
-    for (int s0 = wave; s0 < li.n_slices; s0 += NW * SB) {
-        SliceInfo si[SB];
+    for (int s = wave; s < li.n_slices; s += NW) {
+        const SliceInfo si = L.slice[li.slice_first + s];
+        const bool on = lane < si.width;
+        const int c = s * 64 + lane;
+        // key state of a single-chunk segment, loaded with the first rows
+        const int dkey = on && c >= li.n_slots ? L.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)] : 0;
+        const int col = si.base + min(lane, si.width - 1);
+        LseD acc{-__builtin_huge_val(), 0.0f};
+        for (int r0 = 0; r0 < si.height; r0 += RB) {
+            Elem f[RB];
 #pragma unroll
-        for (int k = 0; k < SB; ++k) {
-            const int s = s0 + k * NW;
-            si[k] = s < li.n_slices ? L.slice[li.slice_first + s] : SliceInfo{0, 0, 0, 0};
+            for (int u = 0; u < RB; ++u) {
+                const int at = col + min(r0 + u, si.height - 1) * si.width;
+                const int32_t o = L.other[at];
+                const float sc = L.score[at];
+                f[u] = on && r0 + u < si.height ? Elem{o, sc} : Elem{dead, 0.0f};
+            }
+            float g[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) g[u] = prev[f[u].other];
+            lse_push_terms<RB>(acc, g, f);
         }
-        Elem e[SB][RB];
-        int dkey[SB];  // key state of a single-chunk segment, loaded with its rows
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-            const bool on = lane < si[k].width;
-            const int32_t *op = L.other + si[k].base + lane;
-            const float *sp = L.score + si[k].base + lane;
-#pragma unroll
-            for (int u = 0; u < RB; ++u)
-                e[k][u] = on && u < si[k].height ? Elem{op[u * si[k].width], sp[u * si[k].width]}
-                                                 : Elem{dead, 0.0f};
-            const int c = (s0 + k * NW) * 64 + lane;
-            dkey[k] = on && c >= li.n_slots ? L.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-            if (lane < si[k].width) {
-                LseD acc{-__builtin_huge_val(), 0.0f};
-                {
-                    float g[RB];
-#pragma unroll
-                    for (int u = 0; u < RB; ++u) g[u] = prev[e[k][u].other];
-                    lse_push_terms<RB>(acc, g, e[k]);
-                }
-                for (int r0 = RB; r0 < si[k].height; r0 += RB) {
-                    Elem f[RB];
-#pragma unroll
-                    for (int u = 0; u < RB; ++u)
-                        f[u] = r0 + u < si[k].height
-                                   ? Elem{L.other[si[k].base + (r0 + u) * si[k].width + lane],
-                                          L.score[si[k].base + (r0 + u) * si[k].width + lane]}
-                                   : Elem{dead, 0.0f};
-                    float g[RB];
-#pragma unroll
-                    for (int u = 0; u < RB; ++u) g[u] = prev[f[u].other];
-                    lse_push_terms<RB>(acc, g, f);
-                }
-                const int c = (s0 + k * NW) * 64 + lane;
-                const double v = lse_value_d(acc);
-                if (c < li.n_slots) {
-                    part[c] = v;  // a chunk of a multi-chunk segment, in log form
-                } else {
-                    const int j = li.n_multi + (c - li.n_slots);
-                    vval[j] = v;
-                    vkey[j] = dkey[k];
-                    my_max = fmax(my_max, v);
-                }
+        if (on) {
+            const double v = lse_value_d(acc);
+            if (c < li.n_slots) {
+                part[c] = v;  // a chunk of a multi-chunk segment, in log form
+            } else {
+                const int j = li.n_multi + (c - li.n_slots);
+                vval[j] = v;
+                vkey[j] = dkey;
+                my_max = fmax(my_max, v);
             }
         }
     }
@@ -620,7 +602,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             } else {
                 tape = tp.alpha + bv.tok_off[i];
             }
-            const double mx = lse_step<NT, 1, kRowBatch>(fl, li, prev, part, vval, vkey, lane, wave, Q);
+            const double mx = lse_step<NT, kRowBatch>(fl, li, prev, part, vval, vkey, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
