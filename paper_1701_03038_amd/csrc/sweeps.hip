@@ -968,9 +968,11 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     for (int r0 = 0; r0 < si.height; r0 += RB) {
                         Elem e[RB];
 #pragma unroll
-                        for (int u = 0; u < RB; ++u) {
-                            const int pos = si.base + (r0 + u) * si.width + l;
-                            e[u] = r0 + u < si.height ? Elem{rl.other[pos], rl.score[pos]} : Elem{Q, 0.0f};
+                        for (int u = 0; u < RB; ++u) {  // no branches: all RB loads in flight together
+                            const int pos = si.base + min(r0 + u, si.height - 1) * si.width + l;
+                            const int32_t o = rl.other[pos];
+                            const float sc = rl.score[pos];
+                            e[u] = r0 + u < si.height ? Elem{o, sc} : Elem{Q, 0.0f};
                         }
                         float g[RB];
 #pragma unroll
