@@ -199,6 +199,26 @@ int wfst_forward_backward(const wfst_fst *fst, int32_t batch, int64_t num_tokens
                           float *arc_posterior, float *final_posterior, int32_t *status,
                           void *stream);
 
+/*
+ * Autotuner for batched decoding and training (the batching step of the
+ * method: one persistent workgroup per sentence at a time).  Times one batched
+ * Viterbi + forward + backward pass on the given batch (offsets/tokens as in
+ * wfst_viterbi, DEVICE) for each workgroup size per sentence in
+ * {64, 128, 256, 512, 1024}, after one untimed pass per size, and keeps the
+ * fastest for later calls on this FST (as if it had been created with that
+ * threads_per_sentence).  Results of every call stay exact for every size
+ * (Viterbi bit-exact, forward-backward within its stated accuracy); only
+ * speed changes.
+ *   threads_out: HOST int32 or NULL, receives the chosen size.
+ *   times_ms: HOST float[5] or NULL, milliseconds per pass for each size in
+ *     the order above; -1 for a size the FST's LDS needs do not allow.
+ * Allocates and frees its own scratch outputs (one float per arc among them)
+ * and synchronises the stream: call it off the hot path.  On error the FST
+ * keeps its previous size.
+ */
+int wfst_fst_autotune(wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                      const int32_t *tokens, int32_t *threads_out, float *times_ms, void *stream);
+
 /* Message for the last nonzero return on this thread ("" if none). */
 const char *wfst_last_error(void);
 

@@ -62,7 +62,7 @@ EXPORTS = (
     "wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_destroy", "wfst_fst_get_info", "wfst_fst_health",
     "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats",
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
-    "wfst_forward_backward", "wfst_last_error", "wfst_layout_host",
+    "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
 )
 
 
@@ -95,9 +95,11 @@ def load_library(path: str | None = None):
     lib.wfst_last_error.argtypes = []
     lib.wfst_last_error.restype = ctypes.c_char_p
     lib.wfst_layout_host.argtypes = [i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
+    lib.wfst_fst_autotune.argtypes = [P, i32, i64, P, P, ctypes.POINTER(i32), P, P]
     for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health",
                  "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats", "wfst_viterbi",
-                 "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host"):
+                 "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
+                 "wfst_fst_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -212,6 +214,17 @@ class Fst:
             if t is not None and (not t.is_cuda or t.dtype.itemsize != 4 or not t.is_contiguous()):
                 raise WfstError(WFST_EINVAL, "scores must be contiguous float32 device tensors")
         _check(_lib.wfst_fst_set_scores(self.handle, _dptr(arc_score), _dptr(final_score), _stream()))
+
+    def autotune(self, offsets, tokens):
+        """Time batched Viterbi + forward + backward on this batch for each workgroup size
+        per sentence and keep the fastest; returns (size, {size: ms or None if it does not fit})."""
+        off, tok, B, N = _batch(offsets, tokens)
+        chosen = ctypes.c_int32(0)
+        ms = np.zeros(5, np.float32)
+        _check(_lib.wfst_fst_autotune(self.handle, B, N, _dptr(off), _dptr(tok), ctypes.byref(chosen),
+                                      _np_ptr(ms), _stream()))
+        return int(chosen.value), {n: (float(t) if t >= 0 else None)
+                                   for n, t in zip((64, 128, 256, 512, 1024), ms)}
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -1260,4 +1260,76 @@ int wfst_forward_backward(const wfst_fst *f, int32_t batch, int64_t num_tokens, 
     return rc;
 }
 
+int wfst_fst_autotune(wfst_fst *f, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                      const int32_t *tokens, int32_t *threads_out, float *times_ms, void *stream)
+{
+    if (!f) return set_err(WFST_EINVAL, "fst is NULL");
+    TRY(check_batch(f, batch, num_tokens, offsets, tokens));
+    static const int32_t sizes[5] = {64, 128, 256, 512, 1024};
+    float ms[5] = {-1.0f, -1.0f, -1.0f, -1.0f, -1.0f};
+    hipStream_t s = as_stream(stream);
+    const int32_t keep = f->nt;
+    if (batch == 0) {
+        if (threads_out) *threads_out = keep;
+        if (times_ms) std::copy(ms, ms + 5, times_ms);
+        return WFST_OK;
+    }
+    // scratch outputs of the timed passes
+    const int64_t N = num_tokens;
+    const size_t bytes = (size_t)batch * (2 * sizeof(float) + sizeof(int32_t)) + (size_t)N * sizeof(int32_t) +
+                         (size_t)std::max<int64_t>(f->A, 1) * sizeof(float);
+    void *scratch = nullptr;
+    if (hipMalloc(&scratch, bytes) != hipSuccess) return set_err(WFST_ENOMEM, "autotune scratch");
+    float *score = static_cast<float *>(scratch);
+    float *log_z = score + batch;
+    int32_t *status = reinterpret_cast<int32_t *>(log_z + batch);
+    int32_t *arcs = status + batch;
+    float *grad = reinterpret_cast<float *>(arcs + N);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = WFST_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = set_err(WFST_EHIP, "event");
+    auto pass = [&]() -> int {
+        TRY(wfst_viterbi(f, batch, N, offsets, tokens, score, arcs, nullptr, status, s));
+        wfst_tape *t = nullptr;
+        TRY(wfst_forward(f, batch, N, offsets, tokens, log_z, status, &t, s));
+        const int r = wfst_backward(f, t, nullptr, grad, nullptr, s);
+        wfst_tape_free(t);
+        return r;
+    };
+    int best = -1;
+    for (int k = 0; k < 5 && rc == WFST_OK; ++k) {
+        f->nt = sizes[k];
+        int r = pass();  // untimed: grows workspaces, loads code
+        if (r == WFST_EUNSUPPORTED) continue;  // this size does not fit the FST's LDS needs
+        if (r != WFST_OK) {
+            rc = r;
+            break;
+        }
+        if (hipEventRecord(e0, s) != hipSuccess) {
+            rc = set_err(WFST_EHIP, "event");
+            break;
+        }
+        if ((r = pass()) != WFST_OK) {
+            rc = r;
+            break;
+        }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms[k], e0, e1) != hipSuccess) {
+            rc = set_err(WFST_EHIP, "event timing");
+            break;
+        }
+        if (best < 0 || ms[k] < ms[best]) best = k;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(scratch);
+    if (rc == WFST_OK && best < 0) rc = set_err(WFST_EUNSUPPORTED, "no workgroup size fits this FST");
+    f->nt = rc == WFST_OK ? sizes[best] : keep;
+    if (rc != WFST_OK) return rc;
+    if (threads_out) *threads_out = f->nt;
+    if (times_ms) std::copy(ms, ms + 5, times_ms);
+    return WFST_OK;
+}
+
 }  // extern "C"
