@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--per-sentence", type=int, default=512,
                     help="sentences run one per call for the per-sentence form (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="sentences timed on the CPU oracle (0: skip)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the workgroup size per sentence with wfst_fst_autotune on this batch (untimed)")
     ap.add_argument("--threads", type=int, default=0,
                     help="workgroup size per sentence of the sweeps (64..1024; 0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -201,6 +203,12 @@ def main():
     tok = torch.as_tensor(batch.tokens, device=dev)
     theta = torch.as_tensor(fst.arc_score, device=dev)
     n_sym = int(batch.offsets[-1])
+    tuned = None
+    if args.autotune:
+        d.set_scores(theta)
+        chosen, times = d.autotune(off, tok)
+        tuned = {"threads_per_sentence": chosen, "ms_per_pass": times}
+        log(f"autotune: {chosen} threads per sentence; ms per pass {times}")
 
     def step():
         d.set_scores(theta)
@@ -309,7 +317,8 @@ def main():
                                "(lognormal lengths mean 25 in [5,60], Zipf(1.1) tokens), seed 0",
                    "step": "set_scores + batched Viterbi with backtrace + batched forward (log Z) + "
                            "batched backward with expected counts over all arcs",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "threads_per_sentence": tuned["threads_per_sentence"] if tuned else (args.threads or 256)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
