@@ -878,24 +878,16 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             for (int s = tid; s < min(li.n_slices, kSliceCache); s += NT) scache[s] = rl.slice[li.slice_first + s];
             if (tid == 0) s_count = 0;
             __syncthreads();
-            // B: reverse segments of w_t whose source is marked (their keys were
-            // loaded last step; compacted before this step's stores are issued)
+            if (rec) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
+            if (t < t1) {  // tape of beta^_t (this step's input), normalised at the end of step t+1
+                float *tape = beta_slot(tp, bk, bv, b, o0, i);
 #pragma unroll
-            for (int u = 0; u < RPF; ++u) {
-                if (rk[u] >= 0 && mark[rk[u]] == t) {
-                    const int pos = atomicAdd(&s_count, 1);
-                    if (pos < list_cap) list[pos] = make_int2(tid + u * NT, rk[u]);
-                }
+                for (int u = 0; u < TPF; ++u)
+                    if (tk_prev[u] >= 0) tape[tid + u * NT] = prev[tk_prev[u]];
+                for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
+                    tape[j] = prev[fl.seg_key[lf_prev.seg_first + j]];
             }
-            for (int j = tid + RPF * NT; j < li.n_segs; j += NT) {
-                const int key = rl.seg_key[li.seg_first + j];
-                if (mark[key] == t) {
-                    const int pos = atomicAdd(&s_count, 1);
-                    if (pos < list_cap) list[pos] = make_int2(j, key);
-                }
-            }
-            // next step's labels and keys, in flight during this step; their
-            // address chain is waited on before any store of the step is issued
+            // next step's labels and keys, in flight during this step
             LabelInfo li_n{}, lf_n{};
             int rk_n[RPF], tk_n[TPF];
             float ta_n[TPF];
@@ -933,15 +925,20 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     }
                 }
             }
-            float *btape = t < t1 ? beta_slot(tp, bk, bv, b, o0, i) : nullptr;  // before the stores
-            if (rec) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
-            if (t < t1) {  // tape of beta^_t (this step's input), normalised at the end of step t+1
-                float *tape = btape;
+            // B: reverse segments of w_t whose source is marked
 #pragma unroll
-                for (int u = 0; u < TPF; ++u)
-                    if (tk_prev[u] >= 0) tape[tid + u * NT] = prev[tk_prev[u]];
-                for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
-                    tape[j] = prev[fl.seg_key[lf_prev.seg_first + j]];
+            for (int u = 0; u < RPF; ++u) {
+                if (rk[u] >= 0 && mark[rk[u]] == t) {
+                    const int pos = atomicAdd(&s_count, 1);
+                    if (pos < list_cap) list[pos] = make_int2(tid + u * NT, rk[u]);
+                }
+            }
+            for (int j = tid + RPF * NT; j < li.n_segs; j += NT) {
+                const int key = rl.seg_key[li.seg_first + j];
+                if (mark[key] == t) {
+                    const int pos = atomicAdd(&s_count, 1);
+                    if (pos < list_cap) list[pos] = make_int2(j, key);
+                }
             }
             __syncthreads();
             int n = s_count;
