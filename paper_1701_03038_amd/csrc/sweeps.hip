@@ -842,30 +842,6 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 }
             }
         }
-        // the address chain runs ahead of its use: labels (and the alpha~ tape
-        // pointer) one step ahead of the keys, tokens one step ahead of the labels
-        LabelInfo li_a{}, lf_a{};     // labels of step t-1 (at the loop top)
-        const float *ap_a = nullptr;  // alpha~ tape of w_{t-2} (records)
-        int tr_a = 0, tf_a = 0;       // tokens of step t-2: w_{t-2} and w_{t-3}
-        int64_t off_a = 0;            // tape offset of w_{t-3}
-        {
-            const int s1 = t1 - 1;
-            if (s1 > t0) {
-                li_a = rl.label[bv.tokens[o0 + s1 - 1]];
-                if (s1 >= 2) {
-                    lf_a = fl.label[bv.tokens[o0 + s1 - 2]];
-                    if (rec) ap_a = alpha_slot(tp, bk, bv, b, o0, o0 + s1 - 2);
-                }
-            }
-            const int s2 = t1 - 2;
-            if (s2 > t0) {
-                tr_a = bv.tokens[o0 + s2 - 1];
-                if (s2 >= 2) {
-                    tf_a = bv.tokens[o0 + s2 - 2];
-                    off_a = bv.tok_off[o0 + s2 - 2];
-                }
-            }
-        }
         LabelInfo lf_prev{};  // forward label of w_t: support of beta~_t, reset after the step
         int tk_prev[TPF];
 #pragma unroll
@@ -911,9 +887,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
                     tape[j] = prev[fl.seg_key[lf_prev.seg_first + j]];
             }
-            // next step's keys, in flight during this step (its labels were loaded
-            // a step ago); then the labels of step t-2 and the tokens of step t-3
-            LabelInfo li_n = li_a, lf_n = lf_a;
+            // next step's labels and keys, in flight during this step
+            LabelInfo li_n{}, lf_n{};
             int rk_n[RPF], tk_n[TPF];
             float ta_n[TPF];
             float cm_n = 0.0f;
@@ -926,6 +901,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 ta_n[u] = WFST_NINF;
             }
             if (t - 1 > t0) {
+                li_n = rl.label[bv.tokens[i - 1]];
 #pragma unroll
                 for (int u = 0; u < RPF; ++u) {
                     const int j = tid + u * NT;
@@ -933,7 +909,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 }
                 if (t - 1 >= 2) {
                     const int ip = i - 2;
-                    const float *ap = ap_a;
+                    lf_n = fl.label[bv.tokens[ip]];
+                    const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
                     if (rec) {
                         cm_n = tp.a_max[ip];
                         aC_n = tp.a_log[ip];
@@ -945,27 +922,6 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                             tk_n[u] = fl.seg_key[lf_n.seg_first + j];
                             if (rec) ta_n[u] = ap[j];
                         }
-                    }
-                }
-            }
-            {
-                const int s1 = t - 2;  // labels of step t-2 from the tokens loaded a step ago
-                li_a = LabelInfo{};
-                lf_a = LabelInfo{};
-                ap_a = nullptr;
-                if (s1 > t0) {
-                    li_a = rl.label[tr_a];
-                    if (s1 >= 2) {
-                        lf_a = fl.label[tf_a];
-                        if (rec) ap_a = bk.c == 0 ? tp.alpha + off_a : alpha_slot(tp, bk, bv, b, o0, o0 + s1 - 2);
-                    }
-                }
-                const int s2 = t - 3;  // tokens of step t-3
-                if (s2 > t0) {
-                    tr_a = bv.tokens[o0 + s2 - 1];
-                    if (s2 >= 2) {
-                        tf_a = bv.tokens[o0 + s2 - 2];
-                        off_a = bv.tok_off[o0 + s2 - 2];
                     }
                 }
             }
@@ -1111,10 +1067,6 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             for (int u = 0; u < TPF; ++u) tk_prev[u] = tk[u];
             li = li_n;
             lf = lf_n;
-            li_a = uniform_label(li_a);  // loaded during this step: kept in scalars
-            lf_a = uniform_label(lf_a);
-            tr_a = wave_uniform(tr_a);
-            tf_a = wave_uniform(tf_a);
             aC = aC_n;
             cm = cm_n;
 #pragma unroll
