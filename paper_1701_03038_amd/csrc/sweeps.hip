@@ -246,10 +246,6 @@ __device__ int check_sentence(const BatchView &bv, int b, int &o0, int &o1)
 // Viterbi (max-plus with back-pointers, paper section 5.1)
 // =====================================================================
 
-struct VEnt {
-    float v;      // alpha_t[q]
-    int32_t idx;  // segment index of q at step t (to chain back-pointers)
-};
 struct VPart {
     float v;
     int32_t pos;   // winning element
@@ -265,9 +261,13 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem[];
-    VEnt *val0 = reinterpret_cast<VEnt *>(smem);
-    VEnt *val1 = val0 + (Q + 1);
-    VPart *part = reinterpret_cast<VPart *>(val1 + (Q + 1));
+    // alpha_t and, per state, its segment index at step t (to chain back-pointers;
+    // a segment index is below Q + 1, which the host keeps under 2^16)
+    float *val0 = reinterpret_cast<float *>(smem);
+    float *val1 = val0 + (Q + 1);
+    uint16_t *idx0 = reinterpret_cast<uint16_t *>(val1 + (Q + 1));
+    uint16_t *idx1 = idx0 + (Q + 1);
+    VPart *part = reinterpret_cast<VPart *>(smem + (size_t)12 * (Q + 1));
     __shared__ int s_item;
     __shared__ unsigned long long s_best[NW];
 
@@ -302,18 +302,25 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
         }
         const int T = o1 - o0;
         for (int q = tid; q <= Q; q += NT) {
-            val0[q] = VEnt{WFST_NINF, -1};
-            val1[q] = VEnt{WFST_NINF, -1};
+            val0[q] = WFST_NINF;
+            val1[q] = WFST_NINF;
+            idx0[q] = 0xffff;
+            idx1[q] = 0xffff;
         }
         __syncthreads();
-        if (tid == 0) val0[start] = VEnt{0.0f, 0};
+        if (tid == 0) {
+            val0[start] = 0.0f;
+            idx0[start] = 0;
+        }
         __syncthreads();
 
         LabelInfo li_next = T > 0 ? fl.label[bv.tokens[o0]] : LabelInfo{};
         LabelInfo lp{};  // label of the previous step (its support is reset)
         for (int t = 1; t <= T; ++t) {
-            VEnt *prev = (t & 1) ? val0 : val1;
-            VEnt *cur = (t & 1) ? val1 : val0;
+            float *prev = (t & 1) ? val0 : val1;
+            float *cur = (t & 1) ? val1 : val0;
+            const uint16_t *prev_idx = (t & 1) ? idx0 : idx1;
+            uint16_t *cur_idx = (t & 1) ? idx1 : idx0;
             const LabelInfo li = li_next;
             if (t < T) li_next = fl.label[bv.tokens[o0 + t]];  // in flight during this step
             const int64_t toff = bv.tok_off[o0 + t - 1];
@@ -332,7 +339,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                         load_rows(op, sp, si.width, si.height, r0, Q, e);
 #pragma unroll
                         for (int u = 0; u < kRowBatch; ++u) {
-                            const float v = prev[e[u].other].v + e[u].score;
+                            const float v = prev[e[u].other] + e[u].score;
                             if (v > best) {
                                 best = v;
                                 bpos = si.base + (r0 + u) * si.width + lane;
@@ -340,13 +347,16 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                             }
                         }
                     }
-                    const int pred = bpos >= 0 ? prev[bsrc].idx : -1;
+                    const int pred = bpos >= 0 ? (int)prev_idx[bsrc] : -1;
                     if (c < li.n_slots) {
                         part[c] = VPart{best, bpos, pred};
                     } else {
                         const int j = li.n_multi + (c - li.n_slots);
                         const int d = dk;
-                        if (bpos >= 0) cur[d] = VEnt{best, j};
+                        if (bpos >= 0) {
+                            cur[d] = best;
+                            cur_idx[d] = (uint16_t)j;
+                        }
                         bp[toff + j] = make_int2(bpos, pred);
                     }
                 }
@@ -361,21 +371,25 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                     const VPart x = part[sc.first + p];
                     if (x.v > w.v) w = x;
                 }
-                if (w.pos >= 0) cur[d] = VEnt{w.v, j};
+                if (w.pos >= 0) {
+                    cur[d] = w.v;
+                    cur_idx[d] = (uint16_t)j;
+                }
                 bp[toff + j] = make_int2(w.pos, w.pred);
             }
             // clear alpha_{t-1}: its buffer receives alpha_{t+1}
             if (t == 1) {
-                if (tid == 0) prev[start].v = WFST_NINF;
+                if (tid == 0) prev[start] = WFST_NINF;
             } else {
-                for (int j = tid; j < lp.n_segs; j += NT) prev[fl.seg_key[lp.seg_first + j]].v = WFST_NINF;
+                for (int j = tid; j < lp.n_segs; j += NT) prev[fl.seg_key[lp.seg_first + j]] = WFST_NINF;
             }
             lp = li;
             __syncthreads();
         }
 
         // final state: max of alpha_T[q] + f[q]; lowest state id on ties
-        VEnt *fin = (T & 1) ? val1 : val0;
+        const float *fin = (T & 1) ? val1 : val0;
+        const uint16_t *fin_idx = (T & 1) ? idx1 : idx0;
         unsigned long long key = 0ull;
         if (T == 0) {
             if (tid == 0) {
@@ -388,7 +402,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             const LabelInfo li = fl.label[bv.tokens[o1 - 1]];
             for (int j = tid; j < li.n_segs; j += NT) {
                 const int d = fl.seg_key[li.seg_first + j];
-                const float x = fin[d].v;
+                const float x = fin[d];
                 const float f = final_score[d];
                 if (x == WFST_NINF || f == WFST_NINF) continue;
                 const float v = x + f;
@@ -420,7 +434,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             best_score[b] = unord_f32((uint32_t)(best >> 32));
             // backtrace (serial, on device: paper section 5.1)
             const int qT = (int)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
-            int j = T > 0 ? fin[qT].idx : 0;
+            int j = T > 0 ? (int)fin_idx[qT] : 0;
             for (int t = T; t >= 1; --t) {
                 const int2 e = bp[bv.tok_off[o0 + t - 1] + j];
                 path_tmp[o0 + t - 1] = e.x;

@@ -248,7 +248,9 @@ int32_t backward_list_cap(const wfst_fst *f) { return std::max(f->fwd.max_segs, 
 // LDS bytes of each kernel for this FST.
 size_t lds_viterbi(const wfst_fst *f)
 {
-    return (size_t)(f->Q + 1) * 2 * sizeof(VEnt) + (size_t)std::max(f->fwd.max_slots, 1) * sizeof(VPart);
+    // two FP32 value vectors and their 16-bit segment indices, then the chunk partials
+    return (size_t)(f->Q + 1) * 2 * (sizeof(float) + sizeof(uint16_t)) +
+           (size_t)std::max(f->fwd.max_slots, 1) * sizeof(VPart);
 }
 size_t lds_backward(const wfst_fst *f)
 {
@@ -423,6 +425,7 @@ template <int NT>
 int launch_viterbi(const wfst_fst *f, hipStream_t s, const BatchView &bv, int2 *bp, int32_t *path_tmp,
                    float *best_score, int32_t *best_arcs, int32_t *best_olabels)
 {
+    if (f->Q + 1 > 0xffff) return set_err(WFST_EUNSUPPORTED, "Viterbi keeps segment indices in 16 bits: num_states must be < 65535");
     const size_t lds = lds_viterbi(f);
     int grid = 0;
     TRY(persistent_grid(f, viterbi_sweep<NT>, NT, lds, bv.B, &grid));
