@@ -95,6 +95,9 @@ typedef struct wfst_fst_info {
  *     stored as +0.
  *   final_score: host float[num_states], finite or -inf (NaN/+inf -> EINVAL).
  *   start: the start state.  num_arcs < 2^31.
+ * The passes keep per-sentence state vectors in LDS: an FST whose vectors do
+ * not fit a compute unit's LDS makes them return WFST_EUNSUPPORTED with the
+ * size they would need (Viterbi also needs num_states < 65535).
  * The caller keeps ownership of its arrays (they may be freed on return).
  * The library owns *out until wfst_fst_destroy.  Work is queued on `stream`
  * and the call returns after the uploads finished.
