@@ -1844,7 +1844,7 @@ __global__ void __launch_bounds__(256) scatter_scores(float *__restrict__ out_a,
 // then writes both layouts' slots of the label from there, so every score is
 // read from HBM once.  A label whose range exceeds the stage reads directly.
 constexpr int kScoreThreads = 512;
-constexpr int kScoreStage = 12288;  // floats (48 KiB of LDS)
+constexpr int kScoreStage = 10112;  // floats (39.5 KiB of LDS: four workgroups per CU)
 
 constexpr int kScoreUnroll = 8;  // elements per thread in flight
 
