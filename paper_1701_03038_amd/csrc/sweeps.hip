@@ -616,7 +616,8 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             } else {
                 tape = tp.alpha + bv.tok_off[i];
             }
-            const double mx = lse_step<NT, kRowBatch>(fl, li, prev, part, vval, vkey, lane, wave, Q);
+            // 8-row batches: 83 VGPRs, five workgroups per CU (16 rows: 105, four)
+            const double mx = lse_step<NT, 8>(fl, li, prev, part, vval, vkey, lane, wave, Q);
             if (t == 1) {
                 if (tid == 0) prev[start] = WFST_NINF;
             } else {
