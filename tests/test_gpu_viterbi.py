@@ -112,6 +112,25 @@ def test_bad_offsets_flagged(wf):
     assert status.tolist() == [0, 3]
 
 
+def test_too_many_states_rejected(wf):
+    # a state vector that can not live in LDS (and, for Viterbi, segment indices
+    # beyond 16 bits) is refused with WFST_EUNSUPPORTED before any sweep runs
+    say("case: 70000 states rejected")
+    Q = 70000
+    src = np.array([0, 1, 2], np.int32)
+    dst = np.array([1, 2, Q - 1], np.int32)
+    lab = np.array([0, 0, 1], np.int32)
+    fin = np.full(Q, -np.inf, np.float32)
+    fin[Q - 1] = 0.0
+    d = wf.Fst(Q, 2, 0, src, dst, lab, np.zeros(3, np.float32), fin)
+    with pytest.raises(wf.WfstError) as e:
+        wf.viterbi(d, np.array([0, 2], np.int32), np.array([0, 1], np.int32))
+    assert e.value.code == wf.WFST_EUNSUPPORTED
+    with pytest.raises(wf.WfstError) as e:
+        wf.forward(d, np.array([0, 2], np.int32), np.array([0, 1], np.int32))
+    assert e.value.code == wf.WFST_EUNSUPPORTED
+
+
 def test_rejects_bad_scores(wf):
     _, fst, _ = fig1_fst()
     sc = fst.arc_score.copy()
