@@ -15,10 +15,14 @@ One step = the whole path over the batch:
      sum log Z), written densely over all arcs.
 value = input symbols per second = (sum of sentence lengths) / step time.
 
-Also reported: per-kernel times (HIP events on the call stream), the HBM
-roofline of the dominant kernel, the plain per-sentence form (the same
-kernels called with one sentence per call) and the CPU oracle on a bounded
-sample of the batch, on this host.
+Also reported: per-kernel times (HIP events on the call stream) with the
+method's bytes per launch and their fraction of the HBM peak (and of a live
+1 GiB copy's bandwidth), the plain per-sentence form (the same kernels called
+with one sentence per call), the training step on the 1024-sentence batch of
+the same FST through torch.autograd, the bigram tagger (vocabulary 200k,
+16384 sentences of length 1..200) batched against per-sentence, and the CPU
+oracle on a bounded sample of the batch on this host, on one thread and on
+all of them.
 """
 from __future__ import annotations
 
@@ -48,102 +52,112 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def live_arcs(fst, batch):
-    """Per token (b, t) with label a and previous label p (the start state at
-    t = 1): L = number of arcs with input a leaving a state p can reach, i.e.
-    the arcs whose source alpha_{t-1} can occupy.  Cached per (p, a)."""
-    import numpy as np
-    il = fst.ilabel
-    if np.all(il[1:] >= il[:-1]):
-        order = None
-        start = np.searchsorted(il, np.arange(fst.num_ilabels + 1))
-    else:
-        order = np.argsort(il, kind="stable")
-        start = np.searchsorted(il[order], np.arange(fst.num_ilabels + 1))
-
-    def arcs_of(a):
-        sl = slice(start[a], start[a + 1])
-        return sl if order is None else order[sl]
-
-    dsts, cache = {}, {}
-    L = np.zeros(batch.tokens.size, np.int64)
-    offs = batch.offsets
-    for bi in range(batch.size):
-        for i in range(int(offs[bi]), int(offs[bi + 1])):
-            a = int(batch.tokens[i])
-            p = int(batch.tokens[i - 1]) if i > offs[bi] else -1
-            key = (p, a)
-            if key not in cache:
-                if p not in dsts:
-                    dsts[p] = np.array([fst.start]) if p < 0 else np.unique(fst.dst[arcs_of(p)])
-                cache[key] = int(np.isin(fst.src[arcs_of(a)], dsts[p], assume_unique=False).sum())
-            L[i] = cache[key]
-    return L
-
-
-def algorithmic_bytes(fst_dev, fst, batch):
-    """Bytes each kernel must move per launch (one batch).  A, D, D' are the
-    arcs, destination segments and source segments of a label; L the arcs of
-    the token's label leaving states the previous step can reach; p the
-    previous token's label.
-      Viterbi 8A + 12D (arcs {state, score}, segment table, back-pointer),
-      forward 8A + 8D (arcs, segment table, tape write), per token;
-      backward 4D'(a) + 8L + 8D(p) per token (source keys of the label, the
-        arcs of the marked segments, keys and tape of the states computed);
-      counts 8A + 4D' per work item (arc ids and gradient writes, source keys)
-        plus 8D(p) + 8D(a) + 8L per visit (alpha, beta and their keys, live arcs);
-      score scatter 24 per arc (two layouts: arc id, score read, score write),
-      gradient fill 4 per arc."""
+def algorithmic_bytes(fst_dev, batch, Q=None):
+    """Bytes the method moves per launch (one batch), per input symbol (b, t)
+    with label a (A_a arcs, D_a destination segments, D'_a source segments):
+      Viterbi   8 A_a + 8 D_a + 4 D_a  (arcs {state, score}, segment (dst, end), back-pointer write)
+      forward   8 A_a + 8 D_a          (arcs, segment table)
+      backward  8 A_a + 8 D'_a         (the same over the reverse layout)
+      counts    16 A_a per label the batch reads ({src, dst, score} + gradient write)
+      score update 24 per arc (two layouts: arc id, score gather, score write)
+      gradient fill 4 per arc.
+    With Q given (state vectors too large for on-chip memory) every pass also
+    gathers 4 A_a and writes 4 D_a (4 D'_a) per symbol and the counts stream
+    alpha and beta, 8 Q per visit."""
     import numpy as np
     arcs, dseg, rseg = (x.astype(np.int64) for x in fst_dev.label_stats())
     tokens = batch.tokens
     A_tot = int(arcs.sum())
-    first = np.zeros(tokens.size, bool)
-    first[batch.offsets[:-1][batch.lengths() > 0]] = True
-    prev = np.roll(tokens, 1)
-    d_prev = np.where(first, 1, dseg[prev])
-    L = live_arcs(fst, batch)
-    n_vis = np.bincount(tokens, minlength=arcs.size)
-    n_items = (n_vis + 63) // 64
-    return {
+    read = np.bincount(tokens, minlength=arcs.size) > 0
+    out = {
         "viterbi": float((8 * arcs[tokens] + 12 * dseg[tokens]).sum()),
         "forward": float((8 * arcs[tokens] + 8 * dseg[tokens]).sum()),
-        "backward": float((4 * rseg[tokens] + 8 * L + 8 * d_prev).sum()),
-        "counts": float((n_items * (8 * arcs + 4 * rseg)).sum() + (8 * d_prev + 8 * dseg[tokens] + 8 * L).sum()),
+        "backward": float((8 * arcs[tokens] + 8 * rseg[tokens]).sum()),
+        "counts": float(16 * arcs[read].sum()),
         "scores": float(24 * A_tot),
         "grad_fill": float(4 * A_tot),
     }
+    if Q is not None:
+        out["viterbi"] += float((4 * arcs[tokens] + 4 * dseg[tokens]).sum())
+        out["forward"] += float((4 * arcs[tokens] + 4 * dseg[tokens]).sum())
+        out["backward"] += float((4 * arcs[tokens] + 4 * rseg[tokens]).sum())
+        out["counts"] += float(8 * Q * tokens.size)
+    return out
 
 
-def load_traffic(kernel):
-    """Measured HBM bytes per launch from the committed PMC summary, when it was
-    taken on the current kernel sources."""
-    p = os.path.join(ROOT, "profiles", "traffic_trigram_4096.json")
+def kernel_table(prof, bytes_per, traffic=None):
+    """Per kernel: ms per launch (HIP events on the call stream), the method's
+    bytes per launch, their rate and its fraction of the HBM peak; measured
+    HBM bytes per launch from the committed counter summary when current."""
+    kernels = {}
+    for k, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        gbs = bytes_per[k] / (avg * 1e-3) / 1e9
+        row = {"ms_per_launch": round(avg, 4), "launches": n, "alg_bytes_per_launch": bytes_per[k],
+               "alg_GBps": round(gbs, 1), "alg_frac": round(gbs / PEAK_HBM_GBS, 4)}
+        t = (traffic or {}).get(k)
+        if t:
+            row["dram_bytes_per_launch"] = t
+            row["dram_GBps"] = round(t / (avg * 1e-3) / 1e9, 1)
+        kernels[k] = row
+    return kernels
+
+
+def roofline_of(kernels, traffic_total=None):
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"] * kernels[k]["launches"])
+    dk = kernels[dom]
+    return {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(dk["alg_GBps"] / PEAK_HBM_GBS, 4),
+            "traffic": dk.get("dram_bytes_per_launch")}
+
+
+def load_traffic(name="traffic_trigram_4096.json"):
+    """Measured HBM bytes per launch per kernel from a committed PMC summary,
+    when it was taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     with open(p) as f:
         t = json.load(f)
-    if t.get("source_sha") != source_sha() or kernel not in t.get("kernels", {}):
+    if t.get("source_sha") != source_sha():
         return None
-    return t["kernels"][kernel].get("bytes_per_launch")
+    return {k: v.get("bytes_per_launch") for k, v in t.get("kernels", {}).items()}
 
 
-def cpu_baseline(fst, batch, sample):
-    """The C oracle (Viterbi FP32 + forward-backward FP64), single thread, on the
-    first `sample` sentences of the batch."""
-    import numpy as np
-    import oracle
+def _sub_batch(batch, lo, hi):
     import synth
-    sub = synth.Batch(batch.offsets[:sample + 1].copy(), batch.tokens[:int(batch.offsets[sample])].copy())
-    syms = int(sub.offsets[-1])
-    t0 = time.perf_counter()
-    oracle.viterbi(fst, sub)
-    t1 = time.perf_counter()
-    oracle.forward_backward(fst, sub)
-    t2 = time.perf_counter()
-    return {"value": syms / (t2 - t0), "unit": "symbols/s", "cores": 1, "kind": "oracle",
+    o = batch.offsets
+    return synth.Batch((o[lo:hi + 1] - o[lo]).copy(), batch.tokens[int(o[lo]):int(o[hi])].copy())
+
+
+def cpu_baseline(fst, batch, sample, threads=1):
+    """The C oracle (Viterbi FP32 + forward-backward FP64) on the first `sample`
+    sentences of the batch, split into `threads` contiguous parts run on as
+    many host threads (the oracle call releases the interpreter lock)."""
+    import threading
+    import oracle
+    syms = int(batch.offsets[sample])
+    cuts = [round(sample * j / threads) for j in range(threads + 1)]
+    parts = [_sub_batch(batch, cuts[j], cuts[j + 1]) for j in range(threads) if cuts[j + 1] > cuts[j]]
+    tv = tf = 0.0
+    for fn in (oracle.viterbi, oracle.forward_backward):
+        ths = [threading.Thread(target=fn, args=(fst, p)) for p in parts]
+        t0 = time.perf_counter()
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        dt = time.perf_counter() - t0
+        if fn is oracle.viterbi:
+            tv = dt
+        else:
+            tf = dt
+    word = "one thread" if len(parts) == 1 else f"{len(parts)} threads"
+    return {"value": syms / (tv + tf), "unit": "symbols/s", "cores": len(parts), "kind": "oracle",
             "sample": f"first {sample} of {batch.size} sentences ({syms} symbols): oracle Viterbi "
-                      f"{t1 - t0:.2f} s + forward-backward with counts {t2 - t1:.2f} s, one thread",
+                      f"{tv:.2f} s + forward-backward with counts {tf:.2f} s, {word}",
             "host": host_cpu()}
 
 
@@ -158,6 +172,98 @@ def host_cpu():
     return f"{os.cpu_count()} logical CPUs"
 
 
+def time_steps(step, steps, warmup, fst_dev=None):
+    """Warm up, then time `steps` calls of step() between two events on the
+    current stream (synchronised on both sides); ms per step and the library's
+    per-kernel timings (HIP events on the call stream) over the timed region."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if fst_dev is not None:
+        if fst_dev.health() != 0:
+            raise SystemExit(f"kernel health flags {fst_dev.health():#x}")
+        fst_dev.profile(True)
+        fst_dev.profile_read(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(steps, 1)
+    prof = None
+    if fst_dev is not None:
+        prof = fst_dev.profile_read(reset=True)
+        fst_dev.profile(False)
+    return ms, prof
+
+
+def copy_bandwidth(dev, reps=5):
+    """GB/s of a 1 GiB device-to-device copy (read + write bytes), median of reps."""
+    import torch
+    a = torch.ones(2**28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    return sorted(out)[len(out) // 2]
+
+
+def per_sentence_rates(wf, d, batch, off_dev, tok_dev, P):
+    """The plain per-sentence form: the same entry points called with one
+    sentence per call, on the first P sentences."""
+    import torch
+    dev = off_dev.device
+    offs1 = [torch.tensor([0, int(batch.offsets[b + 1] - batch.offsets[b])], dtype=torch.int32, device=dev)
+             for b in range(P)]
+    toks1 = [tok_dev[int(batch.offsets[b]):int(batch.offsets[b + 1])] for b in range(P)]
+    syms = int(batch.offsets[P])
+    for b in range(min(P, 8)):  # warm the workspace
+        wf.viterbi(d, offs1[b], toks1[b])
+        wf.forward_backward(d, offs1[b], toks1[b])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for b in range(P):
+        wf.viterbi(d, offs1[b], toks1[b])
+    torch.cuda.synchronize()
+    tv = time.perf_counter() - t
+    t = time.perf_counter()
+    for b in range(P):
+        _, _, tape = wf.forward(d, offs1[b], toks1[b])
+        wf.backward(d, tape)
+        tape.free()
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t
+    return {"sentences": P, "symbols": syms, "viterbi_symbols_per_s": round(syms / tv, 1),
+            "fwd_bwd_symbols_per_s": round(syms / tf, 1),
+            "viterbi_plus_fwd_bwd_symbols_per_s": round(syms / (tv + tf), 1)}
+
+
+def batched_rates(wf, d, batch, off, tok, steps, warmup):
+    """Batched Viterbi and batched forward + backward (expected counts), timed
+    separately: symbols/s of each and per-kernel timings."""
+    n = int(batch.offsets[-1])
+    ms_v, _ = time_steps(lambda: wf.viterbi(d, off, tok), steps, warmup, d)
+
+    def fb():
+        _, _, tape = wf.forward(d, off, tok)
+        wf.backward(d, tape)
+        tape.free()
+    ms_f, prof = time_steps(fb, steps, warmup, d)
+    return {"viterbi_symbols_per_s": round(n / (ms_v * 1e-3), 1), "viterbi_ms": round(ms_v, 4),
+            "fwd_bwd_symbols_per_s": round(n / (ms_f * 1e-3), 1), "fwd_bwd_ms": round(ms_f, 4)}, prof
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,10 +272,14 @@ def main():
     ap.add_argument("--per-sentence", type=int, default=512,
                     help="sentences run one per call for the per-sentence form (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="sentences timed on the CPU oracle (0: skip)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the multi-threaded oracle timing (0: the host's CPUs, at most 16)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the workgroup size per sentence with wfst_fst_autotune on this batch (untimed)")
     ap.add_argument("--threads", type=int, default=0,
                     help="workgroup size per sentence of the sweeps (64..1024; 0: library default)")
+    ap.add_argument("--only-main", action="store_true",
+                    help="time only the main workload (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -186,6 +296,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     wf.load_library()
+    dev = torch.device("cuda", 0)
+
+    def to_dev(batch):
+        return (torch.as_tensor(batch.offsets.astype(np.int32), device=dev),
+                torch.as_tensor(batch.tokens, device=dev))
 
     log("generating the trigram tagger WFST and 4096 sentences")
     t = time.time()
@@ -198,9 +313,7 @@ def main():
     info = d.info()
     log(f"  done in {time.time() - t:.1f} s, {info['device_bytes'] / 2**30:.2f} GiB on device")
 
-    dev = torch.device("cuda", 0)
-    off = torch.as_tensor(batch.offsets.astype(np.int32), device=dev)
-    tok = torch.as_tensor(batch.tokens, device=dev)
+    off, tok = to_dev(batch)
     theta = torch.as_tensor(fst.arc_score, device=dev)
     n_sym = int(batch.offsets[-1])
     tuned = None
@@ -217,72 +330,70 @@ def main():
         wf.backward(d, tape)
         tape.free()
 
-    log(f"warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    if d.health() != 0:
-        raise SystemExit(f"kernel health flags {d.health():#x}")
-
-    log(f"timing {args.steps} steps")
-    d.profile(True)
-    d.profile_read(reset=True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / max(args.steps, 1)
-    prof = d.profile_read(reset=True)
-    d.profile(False)
+    log(f"timing {args.steps} steps after {args.warmup} warmup steps")
+    ms_step, prof = time_steps(step, args.steps, args.warmup, d)
     health = d.health()
-
-    bytes_per = algorithmic_bytes(d, fst, batch)
-    kernels = {}
-    for k, (ms, n) in prof.items():
-        if n == 0:
-            continue
-        avg = ms / n
-        gbs = bytes_per[k] / (avg * 1e-3) / 1e9
-        kernels[k] = {"ms_per_launch": round(avg, 4), "launches": n, "alg_bytes_per_launch": bytes_per[k],
-                      "alg_GBps": round(gbs, 1)}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"] * kernels[k]["launches"])
-    dk = kernels[dom]
-    traffic = load_traffic(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(dk["alg_GBps"] / PEAK_HBM_GBS, 4), "traffic": traffic}
+    traffic = load_traffic()
+    kernels = kernel_table(prof, algorithmic_bytes(d, batch), traffic)
+    roofline = roofline_of(kernels)
+    copy_gbs = copy_bandwidth(dev)
+    roofline["copy_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
 
     per_sentence = None
-    if args.per_sentence > 0:
+    if args.per_sentence > 0 and not args.only_main:
         P = min(args.per_sentence, batch.size)
         log(f"per-sentence form on {P} sentences (one call per sentence)")
-        offs1 = [torch.tensor([0, int(batch.offsets[b + 1] - batch.offsets[b])], dtype=torch.int32, device=dev)
-                 for b in range(P)]
-        toks1 = [tok[int(batch.offsets[b]):int(batch.offsets[b + 1])] for b in range(P)]
-        syms = int(batch.offsets[P])
-        for b in range(min(P, 8)):  # warm the workspace
-            wf.viterbi(d, offs1[b], toks1[b])
-            wf.forward_backward(d, offs1[b], toks1[b])
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for b in range(P):
-            wf.viterbi(d, offs1[b], toks1[b])
-        torch.cuda.synchronize()
-        tv = time.perf_counter() - t
-        t = time.perf_counter()
-        for b in range(P):
-            _, _, tape = wf.forward(d, offs1[b], toks1[b])
-            wf.backward(d, tape)
-            tape.free()
-        torch.cuda.synchronize()
-        tf = time.perf_counter() - t
-        per_sentence = {"sentences": P, "symbols": syms,
-                        "viterbi_symbols_per_s": round(syms / tv, 1),
-                        "fwd_bwd_symbols_per_s": round(syms / tf, 1),
-                        "viterbi_plus_fwd_bwd_symbols_per_s": round(syms / (tv + tf), 1)}
+        per_sentence = per_sentence_rates(wf, d, batch, off, tok, P)
+
+    training = None
+    if not args.only_main:
+        log("training step on the 1024-sentence batch (LogPartition forward + backward)")
+        _, b3 = synth.config(3)
+        off3, tok3 = to_dev(b3)
+        th3 = torch.tensor(fst.arc_score, device=dev, requires_grad=True)
+
+        def train_step():
+            th3.grad = None
+            lz, _ = wf.log_partition(th3, d, off3, tok3)
+            lz.sum().backward()
+        ms3, prof3 = time_steps(train_step, args.steps, args.warmup, d)
+        k3 = kernel_table(prof3, algorithmic_bytes(d, b3))
+        n3 = int(b3.offsets[-1])
+        total_alg = sum(v["alg_bytes_per_launch"] * v["launches"] for v in k3.values()) / args.steps
+        training = {"workload": f"trigram tagger WFST ({fst.num_arcs} arcs), {b3.size} sentences, {n3} symbols "
+                                "(lognormal lengths mean 25 in [5,60]); loss = sum of log Z; "
+                                "step = set_scores + forward + backward with expected counts through "
+                                "torch.autograd (LogPartition)",
+                    "symbols_per_s": round(n3 / (ms3 * 1e-3), 1), "ms_per_step": round(ms3, 4),
+                    "alg_bytes_per_step": total_alg,
+                    "step_frac": round(total_alg / (ms3 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                    "roofline": roofline_of(k3), "kernels": k3}
+        del b3, off3, tok3, th3
+
+    bigram = None
+    if not args.only_main:
+        log("bigram tagger (vocabulary 200k), 16384 sentences of length 1..200")
+        f4, b4 = synth.config(4)
+        d4 = wf.Fst.from_synth(f4)
+        off4, tok4 = to_dev(b4)
+        chosen4, times4 = d4.autotune(off4, tok4)
+        log(f"  autotune: {chosen4} threads per sentence; ms per pass {times4}")
+        rates4, prof4 = batched_rates(wf, d4, b4, off4, tok4, args.steps, args.warmup)
+        k4 = kernel_table(prof4, algorithmic_bytes(d4, b4))
+        P4 = min(max(args.per_sentence, 1), b4.size)
+        log(f"  per-sentence form on {P4} sentences")
+        ps4 = per_sentence_rates(wf, d4, b4, off4, tok4, P4)
+        bigram = {"workload": f"bigram tagger WFST: 45 tags, 46 states, vocab 200000, {f4.num_arcs} arcs; "
+                              f"{b4.size} sentences, {int(b4.offsets[-1])} symbols (lengths uniform 1..200)",
+                  "autotune": {"threads_per_sentence": chosen4, "ms_per_pass": times4},
+                  "batched": rates4, "per_sentence": ps4,
+                  "batched_over_per_sentence": {
+                      "viterbi": round(rates4["viterbi_symbols_per_s"] / ps4["viterbi_symbols_per_s"], 1),
+                      "fwd_bwd": round(rates4["fwd_bwd_symbols_per_s"] / ps4["fwd_bwd_symbols_per_s"], 1)},
+                  "roofline": roofline_of(k4), "kernels": k4}
+        d4.close()
+        del f4, b4, d4
 
     if args.copy_calibration:
         log("1 GiB device copy (HBM counter reference)")
@@ -293,12 +404,16 @@ def main():
         b2.copy_(a)
         torch.cuda.synchronize()
 
-    cpu = None
+    cpu = cpu_mt = None
     if args.cpu_sample > 0:
-        log(f"CPU oracle on {args.cpu_sample} sentences")
-        cpu = cpu_baseline(fst, batch, min(args.cpu_sample, batch.size))
+        sample = min(args.cpu_sample, batch.size)
+        log(f"CPU oracle on {sample} sentences, one thread")
+        cpu = cpu_baseline(fst, batch, sample)
+        if not args.only_main:
+            nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
+            log(f"CPU oracle on {sample} sentences, {nth} threads")
+            cpu_mt = cpu_baseline(fst, batch, sample, threads=nth)
 
-    batched_parts = {k: kernels[k]["ms_per_launch"] for k in kernels}
     out = {
         "metric": METRIC,
         "value": round(n_sym / (ms_step * 1e-3), 1),
@@ -322,8 +437,11 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
-        "batched_viterbi_symbols_per_s": round(n_sym / (batched_parts.get("viterbi", float("nan")) * 1e-3), 1),
+        "batched_viterbi_symbols_per_s": round(n_sym / (kernels["viterbi"]["ms_per_launch"] * 1e-3), 1),
         "per_sentence": per_sentence,
+        "training_1024": training,
+        "bigram_16384": bigram,
+        "cpu_oracle_threads": cpu_mt,
         "health": health,
         "source_sha": source_sha(),
     }

@@ -34,6 +34,9 @@
  *     sentence b; offsets has batch+1 entries, offsets[0] = 0, non-decreasing,
  *     offsets[batch] = num_tokens (passed by value so that no device read is
  *     needed to size work); num_tokens < 2^31.
+ *   - An FST owns one workspace that every call on it reuses: calls on one
+ *     FST must be issued on one stream (or otherwise ordered); calls on
+ *     different FSTs may overlap.
  */
 #ifndef WFST_H
 #define WFST_H
@@ -107,14 +110,24 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
                     const int32_t *olabel, const float *arc_score, const float *final_score,
                     const wfst_options *options, void *stream, wfst_fst **out);
 
-/* Replace the scores (training): arc_score_dev is a DEVICE float[num_arcs] in
- * arc-id order, scattered into both layouts through the stored permutation;
+/* Replace the scores: the parameter update of training, where the expected
+ * counts of Algorithm 2 feed expectation-maximisation or a gradient step
+ * (paper, section 4).  arc_score_dev is a DEVICE float[num_arcs] in arc-id
+ * order, scattered into both layouts through the stored permutation;
  * final_score_dev (nullable) a DEVICE float[num_states].  Values are not
- * validated (a NaN propagates).  Asynchronous on stream. */
+ * validated (a NaN propagates).  Asynchronous on stream.  Every call bumps
+ * the FST's score version (wfst_fst_score_version): a tape made before the
+ * update can no longer be used by wfst_backward. */
 int wfst_fst_set_scores(wfst_fst *fst, const float *arc_score_dev, const float *final_score_dev,
                         void *stream);
 
-/* Free the FST's device memory (synchronises its device).  NULL-safe. */
+/* *version (host) receives the FST's score version: 0 after creation, plus one
+ * per wfst_fst_set_scores call. */
+int wfst_fst_score_version(const wfst_fst *fst, uint64_t *version);
+
+/* Free the device layouts built by wfst_fst_create (the arrays of section 4 /
+ * Figure 2 in their sliced form) and the FST's workspace.  Synchronises the
+ * FST's device; every tape of the FST must have been freed first.  NULL-safe. */
 void wfst_fst_destroy(wfst_fst *fst);
 
 int wfst_fst_get_info(const wfst_fst *fst, wfst_fst_info *info);
@@ -188,15 +201,22 @@ int wfst_forward(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const i
  * Sentences without a path (or with a bad token) contribute zero.  The sum
  * over b and over visits is taken in a fixed order: results are bitwise
  * reproducible for a given FST, batch and library configuration.
+ * Returns WFST_EINVAL when the FST's scores were replaced (set_scores) after
+ * the forward pass that made the tape: the counts would pair the old alpha
+ * with the new scores.
  */
 int wfst_backward(const wfst_fst *fst, const wfst_tape *tape, const float *grad_log_z,
                   float *grad_arc_score, float *grad_final, void *stream);
 
+/* Return a tape's buffers (the stored forward variables of Algorithm 2, or
+ * their checkpoints) to its FST's pool.  NULL-safe; the FST must still exist. */
 void wfst_tape_free(wfst_tape *tape);
 
-/* forward + backward with g_b = 1: log_z float[batch], arc_posterior
- * float[num_arcs] = sum_b E_b[count_k] (for batch = 1 each value is in [0, n]
- * and they sum to n), final_posterior float[num_states] or NULL. DEVICE memory. */
+/* The whole of Algorithm 2 (forward loop, backward loop, expected counts) with
+ * g_b = 1: log_z float[batch], arc_posterior float[num_arcs] = sum_b
+ * E_b[count_k] (for batch = 1 each value is in [0, n] and they sum to n),
+ * final_posterior float[num_states] or NULL, status int32[batch].  DEVICE
+ * memory, overwritten; errors as wfst_forward and wfst_backward. */
 int wfst_forward_backward(const wfst_fst *fst, int32_t batch, int64_t num_tokens,
                           const int32_t *offsets, const int32_t *tokens, float *log_z,
                           float *arc_posterior, float *final_posterior, int32_t *status,

@@ -63,6 +63,7 @@ EXPORTS = (
     "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats",
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
+    "wfst_fst_score_version",
 )
 
 
@@ -96,8 +97,10 @@ def load_library(path: str | None = None):
     lib.wfst_last_error.restype = ctypes.c_char_p
     lib.wfst_layout_host.argtypes = [i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
     lib.wfst_fst_autotune.argtypes = [P, i32, i64, P, P, ctypes.POINTER(i32), P, P]
+    lib.wfst_fst_score_version.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
     for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health",
-                 "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats", "wfst_viterbi",
+                 "wfst_fst_score_version", "wfst_fst_profile", "wfst_fst_profile_read",
+                 "wfst_fst_label_stats", "wfst_viterbi",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
                  "wfst_fst_autotune"):
         getattr(lib, name).restype = ctypes.c_int
@@ -206,6 +209,12 @@ class Fst:
         """Sticky health bits of the FST's kernels (0 = healthy); synchronises the stream."""
         out = ctypes.c_uint32(0)
         _check(_lib.wfst_fst_health(self.handle, ctypes.byref(out), int(clear), _stream()))
+        return int(out.value)
+
+    def score_version(self) -> int:
+        """Number of score updates so far (a tape only serves backward at the version it was made at)."""
+        out = ctypes.c_uint64(0)
+        _check(_lib.wfst_fst_score_version(self.handle, ctypes.byref(out)))
         return int(out.value)
 
     def set_scores(self, arc_score, final_score=None):
@@ -346,25 +355,42 @@ def _make_log_partition():
         forward(arc_score f32[A] (device), fst, offsets, tokens) -> log_z f32[B].
         The scores are written into the FST's layouts (set_scores); backward
         returns d loss / d arc_score = sum_b g_b E_b[count of each arc].
+        The scores are saved for backward: when another call replaced the
+        FST's scores in between (two log_partition calls on one FST before
+        backward), backward writes the saved scores back and runs the forward
+        pass again, so the counts always pair alpha with its own scores.
         """
 
         @staticmethod
         def forward(ctx, arc_score, fst, offsets, tokens, final_score=None):
-            fst.set_scores(arc_score.detach().contiguous(),
-                           None if final_score is None else final_score.detach().contiguous())
+            th = arc_score.detach().contiguous()
+            fin = None if final_score is None else final_score.detach().contiguous()
+            fst.set_scores(th, fin)
             log_z, status, tape = forward(fst, offsets, tokens)
             ctx.fst, ctx.tape = fst, tape
+            ctx.version = fst.score_version()
+            ctx.batch = (offsets, tokens)
+            ctx.has_final = final_score is not None
             ctx.final = final_score is not None and final_score.requires_grad
+            ctx.save_for_backward(arc_score, final_score)
             ctx.mark_non_differentiable(status)
             return log_z, status
 
         @staticmethod
         def backward(ctx, grad_log_z, _grad_status):
+            arc_score, final_score = ctx.saved_tensors
+            fst, tape = ctx.fst, ctx.tape
+            if fst.score_version() != ctx.version:
+                tape.free()
+                fst.set_scores(arc_score.detach().contiguous(),
+                               final_score.detach().contiguous() if ctx.has_final else None)
+                _, _, tape = forward(fst, *ctx.batch)
             if ctx.final:
-                g, gf = backward(ctx.fst, ctx.tape, grad_log_z, final=True)
+                g, gf = backward(fst, tape, grad_log_z, final=True)
             else:
-                g, gf = backward(ctx.fst, ctx.tape, grad_log_z), None
-            ctx.tape.free()
+                g, gf = backward(fst, tape, grad_log_z), None
+            tape.free()
+            ctx.tape = None
             return g, None, None, None, gf
 
     return LogPartition

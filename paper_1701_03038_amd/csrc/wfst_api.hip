@@ -109,6 +109,7 @@ struct wfst_fst {
     int device = 0;
     int32_t Q = 0, M = 0, start = 0, chunk = 16, nt = 256;
     int32_t ckpt_mode = 0;                        // wfst_options.checkpoint
+    uint64_t score_version = 0;                   // bumped by every score update
     int64_t tape_budget = (int64_t)8 << 30;       // bytes of alpha + beta tape before auto checkpointing
     int64_t A = 0;
     DevLayout fwd, rev;
@@ -139,6 +140,7 @@ struct wfst_fst {
 
 struct wfst_tape {
     const wfst_fst *fst = nullptr;
+    uint64_t score_version = 0;  // the FST's scores the forward pass ran with
     int32_t B = 0;
     int64_t N = 0, total = 0;
     const int32_t *offsets = nullptr, *tokens = nullptr;
@@ -207,7 +209,8 @@ void free_fst(wfst_fst *f)
     for (void *p : f->allocs) (void)hipFree(p);
     for (Buf &b : f->ws) free_buf(b);
     for (TapeBufs *t : f->tape_pool) {
-        for (Buf *b : {&t->order, &t->tok_off, &t->alpha, &t->a_max, &t->a_log, &t->log_z, &t->tiles, &t->total})
+        for (Buf *b : {&t->order, &t->tok_off, &t->alpha, &t->a_max, &t->a_log, &t->log_z, &t->tiles, &t->total,
+                       &t->ck_size, &t->ck_off, &t->blk_size, &t->blk_base})
             free_buf(*b);
         delete t;
     }
@@ -753,6 +756,7 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
             return set_err(WFST_EINVAL, "threads_per_sentence must be 64, 128, 256, 512 or 1024");
         if (opt.checkpoint < -1 || opt.checkpoint > 2) return set_err(WFST_EINVAL, "checkpoint must be -1, 0, 1 or 2");
         if (opt.tape_budget_bytes < 0) return set_err(WFST_EINVAL, "tape_budget_bytes must be >= 0");
+        if (opt.count_records < -1) return set_err(WFST_EINVAL, "count_records must be >= -1");
 
         hipStream_t s = as_stream(stream);
         wfst_fst *f = new wfst_fst();
@@ -763,7 +767,6 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         f->chunk = L;
         f->nt = nt;
         f->ckpt_mode = opt.checkpoint;
-        if (opt.count_records < -1) return set_err(WFST_EINVAL, "count_records must be >= -1");
         f->rec_off = opt.count_records == -1;
         f->rec_max = opt.count_records > 0 ? opt.count_records : kRecordsMax;
         if (opt.tape_budget_bytes > 0) f->tape_budget = opt.tape_budget_bytes;
@@ -850,6 +853,7 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
 {
     if (!f) return set_err(WFST_EINVAL, "fst is NULL");
     hipStream_t s = as_stream(stream);
+    if (arc_score_dev || final_score_dev) f->score_version += 1;
     if (arc_score_dev && f->A > 0) {
         ProfScope prof(f, s, WFST_KERNEL_SCORES);
         const int64_t quads = (f->fwd.n_elem + 3) / 4 + (f->rev.n_elem + 3) / 4;
@@ -933,6 +937,13 @@ int wfst_fst_health(const wfst_fst *f, uint32_t *flags, int32_t clear, void *str
     return WFST_OK;
 }
 
+int wfst_fst_score_version(const wfst_fst *f, uint64_t *version)
+{
+    if (!f || !version) return set_err(WFST_EINVAL, "NULL argument");
+    *version = f->score_version;
+    return WFST_OK;
+}
+
 int wfst_fst_get_info(const wfst_fst *f, wfst_fst_info *info)
 {
     if (!f || !info) return set_err(WFST_EINVAL, "NULL argument");
@@ -1005,6 +1016,7 @@ int wfst_forward(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const in
     }
     wfst_tape *t = new wfst_tape();
     t->fst = f;
+    t->score_version = f->score_version;
     t->B = batch;
     t->N = N;
     t->offsets = offsets;
@@ -1062,6 +1074,9 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     if (!fc || !tape) return set_err(WFST_EINVAL, "NULL fst or tape");
     if (tape->fst != fc) return set_err(WFST_EINVAL, "tape belongs to another FST");
     if (!grad_arc_score && fc->A > 0) return set_err(WFST_EINVAL, "grad_arc_score is NULL");
+    if (tape->score_version != fc->score_version)
+        return set_err(WFST_EINVAL, "the FST's scores changed after the forward pass of this tape "
+                                    "(wfst_fst_set_scores); run the forward pass again");
     wfst_fst *f = const_cast<wfst_fst *>(fc);
     hipStream_t s = as_stream(stream);
     if (grad_final) TRY(final_posteriors(f, tape, grad_log_z, grad_final, s));

@@ -34,10 +34,10 @@ def test_fig1(wf):
     np.testing.assert_allclose(post, g["expected"]["posteriors"], atol=1e-6)
 
 
-@pytest.mark.skip(reason="this exact case hung on the GPU with an earlier build (device sorts from hipcub, "
-                         "stream-ordered allocation); no cause was shown in the library, so it stays off the GPU. "
-                         "The same inputs pass on the CPU build of the library, and the split-label cases below "
-                         "cover the same paths with other inputs.")
+@pytest.mark.skip(reason="seed 1 at chunk 16 / 256 threads hung the GPU (pytest timeout inside "
+                         "torch.cuda.synchronize after forward_backward) with an earlier build; no cause has "
+                         "been shown, so these exact inputs stay off the GPU. The split-label test below covers "
+                         "the same code paths with other inputs.")
 @pytest.mark.parametrize("chunk,nt", [(16, 256), (1, 64), (3, 128)])
 def test_tiny_random(wf, chunk, nt):
     for seed in range(10):
@@ -49,18 +49,32 @@ def test_tiny_random(wf, chunk, nt):
         assert_fb_parity(fst, batch, d, f"seed={seed}")
 
 
+def _split_label_case(wf, seed, chunk, nt):
+    say(f"case: tiny split fb seed={seed} chunk={chunk} nt={nt}")
+    fst = synth.tiny_random_fst(seed, 2 + seed % 5, 2 + seed % 2, 8 + seed % 9, final_prob=0.9)
+    lens = np.random.default_rng(seed).integers(0, 9, 60)
+    batch = synth.random_batch(seed, fst.num_ilabels, lens)
+    d = wf.Fst.from_synth(fst, chunk_arcs=chunk, threads_per_sentence=nt)
+    assert_fb_parity(fst, batch, d, f"seed={seed}")
+
+
 @pytest.mark.parametrize("chunk,nt", [(16, 256), (2, 64), (5, 128)])
 def test_tiny_split_label_groups(wf, chunk, nt):
     """Labels visited more than 64 times (several count work items), live and
-    dead sentences, empty and one-token sentences.  (Seeds 100-107 of this
-    test hung on the GPU with an earlier build; they stay off the GPU.)"""
+    dead sentences, empty and one-token sentences."""
     for seed in range(200, 208):
-        say(f"case: tiny split fb seed={seed} chunk={chunk} nt={nt}")
-        fst = synth.tiny_random_fst(seed, 2 + seed % 5, 2 + seed % 2, 8 + seed % 9, final_prob=0.9)
-        lens = np.random.default_rng(seed).integers(0, 9, 60)
-        batch = synth.random_batch(seed, fst.num_ilabels, lens)
-        d = wf.Fst.from_synth(fst, chunk_arcs=chunk, threads_per_sentence=nt)
-        assert_fb_parity(fst, batch, d, f"seed={seed}")
+        _split_label_case(wf, seed, chunk, nt)
+
+
+@pytest.mark.skip(reason="seed 101 at chunk 16 / 256 threads hung the GPU (pytest timeout inside "
+                         "torch.cuda.synchronize after forward_backward) with the build that first added the "
+                         "library, which already used its own radix sort and no stream-ordered allocation; "
+                         "no cause has been shown, so these exact inputs stay off the GPU.")
+@pytest.mark.parametrize("chunk,nt", [(16, 256), (2, 64), (5, 128)])
+def test_tiny_split_label_groups_hung_seeds(wf, chunk, nt):
+    """The inputs of the hung case: seeds 100-107 of the split-label test."""
+    for seed in range(100, 108):
+        _split_label_case(wf, seed, chunk, nt)
 
 
 def test_trigram_tiny_split(wf):
@@ -304,3 +318,124 @@ def test_config4_full(wf):
     assert_viterbi_parity(fst, batch, d, "config4 full")
     say("case: config4 full: forward-backward")
     assert_fb_parity(fst, batch, d, "config4 full")
+
+
+def test_autograd_two_calls_one_fst(wf):
+    """Two log_partition calls on one FST before backward: each output's
+    gradient is the expected counts under its own scores (FP64 oracle), and
+    the C ABI refuses a tape whose FST scores were replaced after it was made."""
+    import torch
+    fst, batch = synth.config(1, batch=16)
+    d = wf.Fst.from_synth(fst)
+    new = (fst.arc_score + np.random.default_rng(5).normal(0, 0.3, fst.num_arcs)).astype(np.float32)
+    f2 = synth.Fst(**{**fst.__dict__})
+    f2.arc_score = new
+    th1 = torch.tensor(fst.arc_score, device="cuda", requires_grad=True)
+    th2 = torch.tensor(new, device="cuda", requires_grad=True)
+    lz1, _ = wf.log_partition(th1, d, batch.offsets, batch.tokens)
+    lz2, _ = wf.log_partition(th2, d, batch.offsets, batch.tokens)
+    (lz1.sum() + 2.0 * lz2.sum()).backward()
+    olz1, og1, _, _ = oracle.forward_backward(fst, batch)
+    olz2, og2, _, _ = oracle.forward_backward(f2, batch)
+    assert np.all(np.abs(lz1.detach().cpu().numpy() - olz1) <= 1e-4 * np.maximum(1, np.abs(olz1)))
+    assert np.all(np.abs(lz2.detach().cpu().numpy() - olz2) <= 1e-4 * np.maximum(1, np.abs(olz2)))
+    n_k = visits_per_arc(fst, batch)
+    assert np.all(np.abs(th1.grad.cpu().numpy() - og1) <= 1e-5 * np.maximum(1, n_k))
+    assert np.all(np.abs(th2.grad.cpu().numpy() - 2.0 * og2) <= 2e-5 * np.maximum(1, n_k))
+    _, _, tape = wf.forward(d, batch.offsets, batch.tokens)
+    d.set_scores(th1.detach())
+    with pytest.raises(wf.WfstError) as e:
+        wf.backward(d, tape)
+    assert e.value.code == -1
+    tape.free()
+    assert d.health() == 0
+
+
+def _label_index(fst):
+    """Arc ids grouped by input label (stable): (order, starts)."""
+    order = np.argsort(fst.ilabel, kind="stable")
+    starts = np.zeros(fst.num_ilabels + 1, np.int64)
+    np.cumsum(np.bincount(fst.ilabel, minlength=fst.num_ilabels), out=starts[1:])
+    return order, starts
+
+
+def _fd_oracle(fst, batch, gn, k, index, eps=1e-3):
+    """Central difference of sum_b g_b log Z_b in arc k's score, in the FP64
+    oracle, over the sentences that read arc k's label and the arcs of the
+    labels they read (the other arcs and sentences do not depend on arc k)."""
+    order, starts = index
+    a = int(fst.ilabel[k])
+    sent = np.unique(np.searchsorted(batch.offsets, np.nonzero(batch.tokens == a)[0], side="right") - 1)
+    sb = synth.Batch(np.concatenate([[0], np.cumsum(batch.lengths()[sent])]).astype(np.int64),
+                     np.concatenate([batch.sentence(b) for b in sent]).astype(np.int32))
+    arcs = np.sort(np.concatenate([order[starts[x]:starts[x + 1]] for x in np.unique(sb.tokens)]))
+    sub = synth.Fst(fst.num_states, fst.num_ilabels, fst.start, fst.src[arcs], fst.dst[arcs], fst.ilabel[arcs],
+                    fst.olabel[arcs], fst.arc_score[arcs].copy(), fst.final_score)
+    j = int(np.searchsorted(arcs, k))
+    plus, minus = np.float32(fst.arc_score[k] + eps), np.float32(fst.arc_score[k] - eps)
+    sub.arc_score[j] = plus
+    lp, _, _, _ = oracle.forward_backward(sub, sb, arc_posteriors=False)
+    sub.arc_score[j] = minus
+    lm, _, _, _ = oracle.forward_backward(sub, sb, arc_posteriors=False)
+    return float(np.sum(gn[sent] * (lp - lm)) / (float(plus) - float(minus)))
+
+
+@pytest.mark.slow
+def test_config3_full_log_partition_finite_differences(wf):
+    """The training step as stated: loss = sum_b g_b log Z_b over the 1024
+    sentences of the trigram workload (172M arcs) through LogPartition;
+    the autograd gradient against the FP64 oracle's expected counts on every
+    arc, and against FP64 central differences (eps = 1e-3) on 64 random arcs
+    of labels the batch reads."""
+    import torch
+    say("case: config3 LogPartition: generating")
+    fst, batch = synth.config(3)
+    d = wf.Fst.from_synth(fst)
+    theta = torch.tensor(fst.arc_score, device="cuda", requires_grad=True)
+    g = torch.linspace(0.5, 1.5, batch.size, device="cuda")
+    say("case: config3 LogPartition: forward + backward")
+    lz, st = wf.log_partition(theta, d, batch.offsets, batch.tokens)
+    (lz * g).sum().backward()
+    torch.cuda.synchronize()
+    assert d.health() == 0
+    grad = theta.grad.cpu().numpy().astype(np.float64)
+    gn = g.cpu().numpy().astype(np.float64)
+    say("case: config3 LogPartition: oracle")
+    olz, ograd, _, ost = oracle.forward_backward(fst, batch, grad_log_z=gn)
+    np.testing.assert_array_equal(st.cpu().numpy(), ost)
+    err = np.abs(lz.detach().cpu().numpy() - olz)
+    assert np.all(err <= 1e-4 * np.maximum(1, np.abs(olz)))
+    n_k = visits_per_arc(fst, batch)
+    assert np.all(np.abs(grad - ograd) <= 1e-5 * np.maximum(1, n_k))
+    say("case: config3 LogPartition: finite differences on 64 arcs")
+    # most arcs of a label the batch reads leave a pair state no path reaches
+    # (zero count): 48 arcs with a nonzero oracle count, 16 from all read labels
+    rng = np.random.default_rng(0)
+    live = np.nonzero(ograd != 0)[0]
+    used = np.nonzero(np.isin(fst.ilabel, np.unique(batch.tokens)))[0]
+    ks = np.concatenate([rng.choice(live, 48, replace=False), rng.choice(used, 16, replace=False)])
+    index = _label_index(fst)
+    for k in ks:
+        fd = _fd_oracle(fst, batch, gn, int(k), index)
+        assert abs(fd - ograd[k]) <= 1e-6 * max(1, n_k[k]) + 1e-6, (k, fd, ograd[k])
+        assert abs(grad[k] - fd) <= 1e-5 * max(1, n_k[k]) + 2e-6, (k, fd, grad[k])
+
+
+@pytest.mark.slow
+def test_config4_single_sentence_posteriors_T200(wf):
+    """Bigram workload (vocabulary 200k): sentences of 200 tokens decoded one
+    at a time; every arc's posterior within 1e-5 absolute of the FP64 oracle."""
+    fst, batch = synth.config(4)
+    d = wf.Fst.from_synth(fst)
+    lens = batch.lengths()
+    picks = np.nonzero(lens == 200)[0][:4]
+    assert picks.size > 0
+    for b in picks:
+        say(f"case: config4 single sentence b={b} T=200")
+        toks = batch.sentence(int(b))
+        one = synth.Batch(np.array([0, toks.size], np.int64), toks)
+        lz, post, st = assert_fb_parity(fst, one, d, f"config4 T=200 b={b}")
+        _, opost, _, _ = oracle.forward_backward(fst, one)
+        err = np.abs(post.astype(np.float64) - opost)
+        assert np.max(err) <= 1e-5, f"b={b}: max posterior error {np.max(err):.3g}"
+        assert abs(post.sum() - 200) < 1e-3
