@@ -20,7 +20,9 @@ method's bytes per launch and their fraction of the HBM peak (and of a live
 1 GiB copy's bandwidth), the plain per-sentence form (the same kernels called
 with one sentence per call), the training step on the 1024-sentence batch of
 the same FST through torch.autograd, the bigram tagger (vocabulary 200k,
-16384 sentences of length 1..200) batched against per-sentence, and the CPU
+16384 sentences of length 1..200) batched against per-sentence, the
+training step on the 1M-state power-law WFST (state vectors in global
+memory, counts in fixed point), and the CPU
 oracle on a bounded sample of the batch on this host, on one thread and on
 all of them.
 """
@@ -278,6 +280,8 @@ def main():
                     help="pick the workgroup size per sentence with wfst_fst_autotune on this batch (untimed)")
     ap.add_argument("--threads", type=int, default=0,
                     help="workgroup size per sentence of the sweeps (64..1024; 0: library default)")
+    ap.add_argument("--powerlaw-steps", type=int, default=2,
+                    help="timed training steps on the 1M-state power-law workload (0: skip)")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main workload (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -395,6 +399,37 @@ def main():
         d4.close()
         del f4, b4, d4
 
+    powerlaw = None
+    if not args.only_main and args.powerlaw_steps > 0:
+        log("power-law WFST: 1M states, 50M arcs, 1024 random-walk strings of 100")
+        t = time.time()
+        f5, b5 = synth.config(5)
+        log(f"  generated in {time.time() - t:.1f} s")
+        t = time.time()
+        d5 = wf.Fst.from_synth(f5)
+        log(f"  device layouts in {time.time() - t:.1f} s, {d5.info()['device_bytes'] / 2**30:.2f} GiB")
+        off5, tok5 = to_dev(b5)
+        th5 = torch.tensor(f5.arc_score, device=dev, requires_grad=True)
+
+        def train5():
+            th5.grad = None
+            lz, _ = wf.log_partition(th5, d5, off5, tok5)
+            lz.sum().backward()
+        ms5, prof5 = time_steps(train5, args.powerlaw_steps, 1, d5)
+        k5 = kernel_table(prof5, algorithmic_bytes(d5, b5, Q=f5.num_states))
+        n5 = int(b5.offsets[-1])
+        total5 = sum(v["alg_bytes_per_launch"] * v["launches"] for v in k5.values()) / args.powerlaw_steps
+        powerlaw = {"workload": f"power-law WFST: {f5.num_states} states, {f5.num_arcs} arcs, out-degree "
+                                "~d^-2.1 on [10,5000], labels Zipf(1.0) over 10k, scores -Exp(1); "
+                                f"{b5.size} random-walk strings of 100 ({n5} symbols); CRF training step = "
+                                "LogPartition forward + backward (expected counts = gradient)",
+                    "steps": args.powerlaw_steps, "symbols_per_s": round(n5 / (ms5 * 1e-3), 1),
+                    "ms_per_step": round(ms5, 3), "alg_bytes_per_step": total5,
+                    "step_frac": round(total5 / (ms5 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                    "roofline": roofline_of(k5), "kernels": k5}
+        d5.close()
+        del f5, b5, d5, th5
+
     if args.copy_calibration:
         log("1 GiB device copy (HBM counter reference)")
         a = torch.empty(2**28, dtype=torch.float32, device=dev)
@@ -441,6 +476,7 @@ def main():
         "per_sentence": per_sentence,
         "training_1024": training,
         "bigram_16384": bigram,
+        "powerlaw_1m": powerlaw,
         "cpu_oracle_threads": cpu_mt,
         "health": health,
         "source_sha": source_sha(),

@@ -68,11 +68,19 @@ typedef struct wfst_options {
     int32_t chunk_arcs;         /* arcs per lane chunk in the sliced layouts (1..64); 0 = auto */
     int32_t threads_per_sentence; /* workgroup size per sentence (64,128,256,512,1024); 0 = auto */
     int32_t checkpoint;         /* forward tape: -1/0 = auto, 1 = force sqrt(T) checkpointing, 2 = never */
-    int32_t reserved0;
+    int32_t state_memory;       /* per-sentence state vectors of the sweeps: 0 = auto (LDS when they fit,
+                                   else a slot of global memory per workgroup), 1 = LDS only (larger FSTs
+                                   are refused), 2 = always global memory */
     int64_t tape_budget_bytes;  /* auto mode checkpoints when the full tape exceeds this; 0 = 8 GiB */
     int64_t count_records;      /* expected counts: 0 = auto (per-visit records of the backward pass, sorted
-                                   and summed per arc, while they fit; else the label-grouped count kernel),
-                                   -1 = always the grouped count kernel, > 0 = record capacity per call */
+                                   and summed per arc, while they fit; else the label-grouped count kernel
+                                   when its state fits LDS, else fixed-point accumulation),
+                                   -1 = always the grouped count kernel,
+                                   -2 = always fixed-point accumulation (each posterior added to its arc
+                                   as a 64-bit integer of scale 2^S, S = 61 - floor(log2(num_tokens *
+                                   max(1, max |grad_log_z|))): the sum does not depend on the order),
+                                   > 0 = record capacity per call.  A backward sweep whose state is in
+                                   global memory always uses fixed-point accumulation. */
 } wfst_options;
 
 /* Layout statistics (for tuning and reporting). */
@@ -98,9 +106,10 @@ typedef struct wfst_fst_info {
  *     stored as +0.
  *   final_score: host float[num_states], finite or -inf (NaN/+inf -> EINVAL).
  *   start: the start state.  num_arcs < 2^31.
- * The passes keep per-sentence state vectors in LDS: an FST whose vectors do
- * not fit a compute unit's LDS makes them return WFST_EUNSUPPORTED with the
- * size they would need (Viterbi also needs num_states < 65535).
+ * The passes keep per-sentence state vectors in LDS when they fit (Viterbi
+ * also needs num_states < 65535 there); otherwise each persistent workgroup
+ * keeps them in its own slot of global memory (at most 16 GiB of slots;
+ * fewer sentences then run at once), unless options->state_memory = 1.
  * The caller keeps ownership of its arrays (they may be freed on return).
  * The library owns *out until wfst_fst_destroy.  Work is queued on `stream`
  * and the call returns after the uploads finished.

@@ -40,7 +40,7 @@ class WfstError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("chunk_arcs", ctypes.c_int32), ("threads_per_sentence", ctypes.c_int32),
-                ("checkpoint", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("checkpoint", ctypes.c_int32), ("state_memory", ctypes.c_int32),
                 ("tape_budget_bytes", ctypes.c_int64), ("count_records", ctypes.c_int64)]
 
 
@@ -152,7 +152,7 @@ class Fst:
 
     def __init__(self, num_states, num_ilabels, start, src, dst, ilabel, arc_score, final_score,
                  olabel=None, chunk_arcs=0, threads_per_sentence=0, checkpoint=0, tape_budget_bytes=0,
-                 count_records=0):
+                 count_records=0, state_memory=0):
         import torch
         lib = load_library()
         self.num_states, self.num_ilabels, self.start = int(num_states), int(num_ilabels), int(start)
@@ -161,7 +161,8 @@ class Fst:
         sc = np.ascontiguousarray(arc_score, np.float32)
         fin = np.ascontiguousarray(final_score, np.float32)
         self.num_arcs = int(arrs[0].shape[0])
-        opt = _Options(chunk_arcs, threads_per_sentence, checkpoint, 0, tape_budget_bytes, count_records)
+        opt = _Options(chunk_arcs, threads_per_sentence, checkpoint, state_memory, tape_budget_bytes,
+                       count_records)
         self.device = torch.cuda.current_device()
         h = ctypes.c_void_p()
         _check(lib.wfst_fst_create(self.num_states, self.num_ilabels, self.start, self.num_arcs,

@@ -100,6 +100,11 @@ __device__ __forceinline__ const float *alpha_slot(const TapeView &tp, const Blo
 // Expected-count records written by the backward pass: one per (arc, visit)
 // with a nonzero posterior, key = (arc << 32) | token position.  count may
 // pass cap: records beyond cap are dropped and the caller falls back.
+//
+// Alternatively (acc != null) each posterior is added at once to its arc's
+// fixed-point accumulator: acc[arc] += round(value * 2^S), an integer atomic,
+// so the sum does not depend on the order of the additions (no records, no
+// sort; used when records could not fit, or when asked for).
 struct RecordSink {
     uint64_t *key = nullptr;  // null: no records
     float *val = nullptr;
@@ -107,6 +112,8 @@ struct RecordSink {
     unsigned long long *total = nullptr;  // records (independent of scheduling)
     int64_t cap = 0;
     const float *grad_log_z = nullptr;  // g_b (null = 1)
+    unsigned long long *acc = nullptr;  // [num_arcs] fixed-point sums (two's complement)
+    const double *fx_scale = nullptr;   // device scalar 2^S
 };
 
 // beta~ of token i: the full tape, or the block buffer of the token's block

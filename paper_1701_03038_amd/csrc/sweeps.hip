@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -252,22 +253,45 @@ struct VPart {
     int32_t pred;  // segment index of the winner's source at the previous step
 };
 
-template <int NT>
+// Bytes of the per-sentence state of the Viterbi sweep: two value vectors and
+// two segment-index vectors over Q + 1 states (16-bit indices on chip, 32-bit
+// in global memory), then the chunk partials of multi-chunk segments.
+template <bool GMEM>
+__host__ __device__ constexpr size_t viterbi_state_bytes(int32_t Q)
+{
+    return (size_t)(Q + 1) * 2 * (sizeof(float) + (GMEM ? sizeof(int32_t) : sizeof(uint16_t)));
+}
+
+// The per-sentence state of a persistent workgroup: LDS, or (GMEM) the
+// workgroup's slot of a global scratch buffer when the state vectors of the
+// FST do not fit on chip.  Each workgroup owns its slot for the whole launch.
+template <bool GMEM>
+__device__ __forceinline__ unsigned char *state_base(unsigned char *lds, unsigned char *gscratch, int64_t slot_bytes)
+{
+    if constexpr (GMEM) return gscratch + (size_t)blockIdx.x * (size_t)slot_bytes;
+    else return lds;
+}
+
+template <int NT, bool GMEM>
 __global__ void __launch_bounds__(NT)
 viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ final_score,
               BatchView bv, int2 *__restrict__ bp, int32_t *__restrict__ path_tmp,
               float *__restrict__ best_score, int32_t *__restrict__ best_arcs,
-              int32_t *__restrict__ best_olabels, const int32_t *__restrict__ olabel)
+              int32_t *__restrict__ best_olabels, const int32_t *__restrict__ olabel,
+              unsigned char *__restrict__ gscratch, int64_t slot_bytes)
 {
     constexpr int NW = NT / 64;
-    extern __shared__ __align__(16) unsigned char smem[];
-    // alpha_t and, per state, its segment index at step t (to chain back-pointers;
-    // a segment index is below Q + 1, which the host keeps under 2^16)
+    // segment index of a state's value at step t (to chain back-pointers); a
+    // segment index is below Q + 1, which the host keeps under 2^16 on chip
+    using Idx = std::conditional_t<GMEM, int32_t, uint16_t>;
+    constexpr Idx kNoIdx = GMEM ? Idx(-1) : Idx(0xffff);
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *smem = state_base<GMEM>(lds, gscratch, slot_bytes);
     float *val0 = reinterpret_cast<float *>(smem);
     float *val1 = val0 + (Q + 1);
-    uint16_t *idx0 = reinterpret_cast<uint16_t *>(val1 + (Q + 1));
-    uint16_t *idx1 = idx0 + (Q + 1);
-    VPart *part = reinterpret_cast<VPart *>(smem + (size_t)12 * (Q + 1));
+    Idx *idx0 = reinterpret_cast<Idx *>(val1 + (Q + 1));
+    Idx *idx1 = idx0 + (Q + 1);
+    VPart *part = reinterpret_cast<VPart *>(smem + viterbi_state_bytes<GMEM>(Q));
     __shared__ int s_item;
     __shared__ unsigned long long s_best[NW];
 
@@ -304,8 +328,8 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
         for (int q = tid; q <= Q; q += NT) {
             val0[q] = WFST_NINF;
             val1[q] = WFST_NINF;
-            idx0[q] = 0xffff;
-            idx1[q] = 0xffff;
+            idx0[q] = kNoIdx;
+            idx1[q] = kNoIdx;
         }
         __syncthreads();
         if (tid == 0) {
@@ -319,8 +343,8 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
         for (int t = 1; t <= T; ++t) {
             float *prev = (t & 1) ? val0 : val1;
             float *cur = (t & 1) ? val1 : val0;
-            const uint16_t *prev_idx = (t & 1) ? idx0 : idx1;
-            uint16_t *cur_idx = (t & 1) ? idx1 : idx0;
+            const Idx *prev_idx = (t & 1) ? idx0 : idx1;
+            Idx *cur_idx = (t & 1) ? idx1 : idx0;
             const LabelInfo li = li_next;
             if (t < T) li_next = fl.label[bv.tokens[o0 + t]];  // in flight during this step
             const int64_t toff = bv.tok_off[o0 + t - 1];
@@ -355,7 +379,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                         const int d = dk;
                         if (bpos >= 0) {
                             cur[d] = best;
-                            cur_idx[d] = (uint16_t)j;
+                            cur_idx[d] = (Idx)j;
                         }
                         bp[toff + j] = make_int2(bpos, pred);
                     }
@@ -373,7 +397,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
                 }
                 if (w.pos >= 0) {
                     cur[d] = w.v;
-                    cur_idx[d] = (uint16_t)j;
+                    cur_idx[d] = (Idx)j;
                 }
                 bp[toff + j] = make_int2(w.pos, w.pred);
             }
@@ -389,7 +413,7 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 
         // final state: max of alpha_T[q] + f[q]; lowest state id on ties
         const float *fin = (T & 1) ? val1 : val0;
-        const uint16_t *fin_idx = (T & 1) ? idx1 : idx0;
+        const Idx *fin_idx = (T & 1) ? idx1 : idx0;
         unsigned long long key = 0ull;
         if (T == 0) {
             if (tid == 0) {
@@ -526,13 +550,15 @@ __device__ __forceinline__ void block_max_into(float v, uint32_t *cell, int lane
     if (lane == 0) atomicMax(cell, ord_f32(v));
 }
 
-template <int NT>
+template <int NT, bool GMEM>
 __global__ void __launch_bounds__(NT)
 forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ final_score,
-              BatchView bv, TapeView tp, BlockView bk, float *__restrict__ log_z_out)
+              BatchView bv, TapeView tp, BlockView bk, float *__restrict__ log_z_out,
+              unsigned char *__restrict__ gscratch, int64_t slot_bytes)
 {
     constexpr int NW = NT / 64;
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *smem = state_base<GMEM>(lds, gscratch, slot_bytes);
     float *val0 = reinterpret_cast<float *>(smem);
     float *val1 = val0 + (Q + 1);
     double *vval = reinterpret_cast<double *>(val1 + (Q + 1) + ((Q + 1) & 1));  // [max_segs] step values
@@ -731,18 +757,20 @@ __device__ __forceinline__ void copy_staged_records(const RecordSink &rs, const 
     }
 }
 
-template <int NT>
+template <int NT, bool GMEM>
 __global__ void __launch_bounds__(NT)
 backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                const float *__restrict__ final_score, const float *__restrict__ final_max,
-               BatchView bv, TapeView tp, BlockView bk, int32_t list_cap, RecordSink rs)
+               BatchView bv, TapeView tp, BlockView bk, int32_t list_cap, RecordSink rs,
+               unsigned char *__restrict__ gscratch, int64_t slot_bytes)
 {
     constexpr int RPF = rev_key_prefetch(NT);
     constexpr int TPF = kTapeKeyPrefetch;
     constexpr int RB = 4;
-    extern __shared__ __align__(16) unsigned char smem[];
-    SliceInfo *scache = reinterpret_cast<SliceInfo *>(smem);           // [kSliceCache]
-    float *val0 = reinterpret_cast<float *>(scache + kSliceCache);     // [Q+1]
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *smem = state_base<GMEM>(lds, gscratch, slot_bytes);
+    __shared__ SliceInfo scache[kSliceCache];                          // slice headers of the step's label
+    float *val0 = reinterpret_cast<float *>(smem);                     // [Q+1]
     float *val1 = val0 + (Q + 1);                                      // [Q+1]
     int32_t *mark = reinterpret_cast<int32_t *>(val1 + (Q + 1));       // [Q+1] step stamp of states to compute
     float *aval = reinterpret_cast<float *>(mark + (Q + 1));           // [Q+1] alpha~_{t-1} - c_{t-1} there
@@ -758,6 +786,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const float fmax0 = *final_max;
+    const double fx = rs.acc ? *rs.fx_scale : 0.0;  // fixed-point scale of the accumulators
     if (tid == 0) {
         s_rn = 0;
         s_cbase = 0;
@@ -818,7 +847,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             C = tp.b_log[i1];
         }
         if (tid < 3) s_cmax[tid] = 0u;
-        const bool rec = rs.key != nullptr;
+        const bool rec = rs.key != nullptr || rs.acc != nullptr;  // posteriors of the visits wanted
+        const bool stage = rs.key != nullptr;                       // ... as records
         const float gb = rs.grad_log_z ? rs.grad_log_z[b] : 1.0f;
         const double lz = tp.log_z[b];
 
@@ -893,7 +923,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             for (int s = tid; s < min(li.n_slices, kSliceCache); s += NT) scache[s] = rl.slice[li.slice_first + s];
             if (tid == 0) s_count = 0;
             __syncthreads();
-            if (rec) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
+            if (stage) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
             if (t < t1) {  // tape of beta^_t (this step's input), normalised at the end of step t+1
                 float *tape = beta_slot(tp, bk, bv, b, o0, i);
 #pragma unroll
@@ -1003,7 +1033,14 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                                 if (g[u] != WFST_NINF) v[u] = gb * exp_e((a + e[u].score) + (g[u] + o));
                                 nrec += v[u] != 0.0f;
                             }
-                            if (nrec > 0) {
+                            if (nrec > 0 && !stage) {
+#pragma unroll
+                                for (int u = 0; u < RB; ++u) {
+                                    if (v[u] == 0.0f) continue;
+                                    const int arc = rl.elem_arc[si.base + (r0 + u) * si.width + l];
+                                    atomicAdd(&rs.acc[arc], (unsigned long long)__double2ll_rn((double)v[u] * fx));
+                                }
+                            } else if (nrec > 0) {
                                 int at = atomicAdd(&s_rn, nrec);
 #pragma unroll
                                 for (int u = 0; u < RB; ++u) {
@@ -1043,7 +1080,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     tp.log_z_bwd[b] = v == -__builtin_huge_val() ? -__builtin_huge_val() : C + v;
             }
             C += c;
-            if (rec && tid == 0) {  // place the step's staged records in the workgroup's chunk (copied next step)
+            if (stage && tid == 0) {  // place the step's staged records in the workgroup's chunk (copied next step)
                 const int n = min(s_rn, kRecStage);
                 s_rtotal += (unsigned long long)s_rn;
                 s_rflush = n;
@@ -1906,6 +1943,39 @@ scatter_scores_by_label(const LabelInfo *__restrict__ fl, const LabelInfo *__res
     __syncthreads();
     scatter_label_layout(fl[a], out_f, arc_f, stage, r.x, staged, score);
     scatter_label_layout(rl[a], out_r, arc_r, stage, r.x, staged, score);
+}
+
+// Scale of the fixed-point count accumulators: 2^S with S the largest integer
+// for which N * max(1, max_b |g_b|) * 2^S stays below 2^62, so no sum of
+// posteriors (each at most |g_b|, at most N of them per arc) can overflow.
+// One workgroup.
+__global__ void __launch_bounds__(256) fx_scale_kernel(const float *__restrict__ g, int32_t B, int64_t N,
+                                                       double *__restrict__ scale)
+{
+    __shared__ float red[256];
+    float m = 1.0f;
+    if (g)
+        for (int b = threadIdx.x; b < B; b += 256) m = fmaxf(m, fabsf(g[b]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double bound = (double)red[0] * (double)(N > 0 ? N : 1);
+        const int S = 61 - ilogb(bound);  // bound < 2^(ilogb + 1), so sums stay below 2^62
+        *scale = ldexp(1.0, S);
+    }
+}
+
+// grad[k] = acc[k] / 2^S
+__global__ void fx_to_grad(const unsigned long long *__restrict__ acc, int64_t n, const double *__restrict__ scale,
+                           float *__restrict__ grad)
+{
+    const double inv = 1.0 / *scale;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        grad[i] = (float)((double)(long long)acc[i] * inv);
 }
 
 __global__ void final_max_kernel(const float *__restrict__ fin, int32_t Q, float *__restrict__ out)

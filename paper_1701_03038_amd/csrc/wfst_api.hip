@@ -91,8 +91,12 @@ enum WsSlot {
     W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
-    W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_NUM
+    W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_NUM
 };
+
+// Global memory for the per-workgroup state of sweeps whose state vectors do
+// not fit on chip: at most this many bytes (the persistent grid shrinks to fit).
+constexpr int64_t kStateScratchBudget = (int64_t)16 << 30;
 
 // small device counters kept together (one allocation)
 enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_ITEMQ = 3, C_TOTAL = 4 /* int64 at byte 16 */,
@@ -109,6 +113,8 @@ struct wfst_fst {
     int device = 0;
     int32_t Q = 0, M = 0, start = 0, chunk = 16, nt = 256;
     int32_t ckpt_mode = 0;                        // wfst_options.checkpoint
+    int32_t state_mem = 0;                        // wfst_options.state_memory
+    bool fx_counts = false;                       // counts by fixed-point accumulation (count_records = -2)
     uint64_t score_version = 0;                   // bumped by every score update
     int64_t tape_budget = (int64_t)8 << 30;       // bytes of alpha + beta tape before auto checkpointing
     int64_t A = 0;
@@ -248,17 +254,18 @@ struct ProfScope {
 // Marked segments per backward step: at most the destinations of one label.
 int32_t backward_list_cap(const wfst_fst *f) { return std::max(f->fwd.max_segs, 1); }
 
-// LDS bytes of each kernel for this FST.
-size_t lds_viterbi(const wfst_fst *f)
+// Bytes of each sweep's per-sentence state for this FST (LDS, or one slot of
+// the global scratch when the vectors do not fit on chip).
+size_t lds_viterbi(const wfst_fst *f, bool gmem)
 {
-    // two FP32 value vectors and their 16-bit segment indices, then the chunk partials
-    return (size_t)(f->Q + 1) * 2 * (sizeof(float) + sizeof(uint16_t)) +
+    // two FP32 value vectors and their segment indices, then the chunk partials
+    return (gmem ? viterbi_state_bytes<true>(f->Q) : viterbi_state_bytes<false>(f->Q)) +
            (size_t)std::max(f->fwd.max_slots, 1) * sizeof(VPart);
 }
 size_t lds_backward(const wfst_fst *f)
 {
     const size_t q1 = (size_t)f->Q + 1;
-    return kSliceCache * sizeof(SliceInfo) + 3 * q1 * sizeof(float) + q1 * sizeof(int32_t) +
+    return 3 * q1 * sizeof(float) + q1 * sizeof(int32_t) +
            (size_t)backward_list_cap(f) * (sizeof(int2) + sizeof(double));
 }
 size_t lds_lse(const wfst_fst *f, const DevLayout &l)
@@ -286,6 +293,42 @@ int persistent_grid(const wfst_fst *f, K kernel, int nt, size_t lds, int64_t wor
     HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, lds));
     if (per_cu < 1) return set_err(WFST_EUNSUPPORTED, "kernel does not fit on a compute unit");
     *grid = (int)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)per_cu * f->cu_count));
+    return WFST_OK;
+}
+
+// Where a sweep keeps its per-sentence state, and its persistent grid.
+struct SweepShape {
+    bool gmem = false;
+    int grid = 0;
+    size_t lds = 0;                      // dynamic LDS bytes
+    int64_t slot = 0;                    // bytes of one workgroup's global slot (gmem)
+    unsigned char *scratch = nullptr;    // grid * slot bytes (gmem)
+};
+
+// State memory of a sweep whose state takes lds_bytes on chip or slot_bytes
+// in global memory: LDS unless the options ask for global memory, the state
+// does not fit, or the sweep needs the wide form (need_wide).  The global
+// form's grid is capped so that its slots fit kStateScratchBudget.
+template <class KL, class KG>
+int sweep_shape(wfst_fst *f, hipStream_t s, KL k_lds, KG k_gmem, int nt, size_t lds_bytes, size_t slot_bytes,
+                bool need_wide, int64_t work, SweepShape &sh)
+{
+    const bool fits = lds_bytes <= f->max_lds && !need_wide;
+    sh.gmem = f->state_mem == 2 || (f->state_mem == 0 && !fits);
+    if (!sh.gmem) {
+        if (!fits)
+            return set_err(WFST_EUNSUPPORTED, "the FST's state vectors need " + std::to_string(lds_bytes) +
+                                                  " bytes of LDS per workgroup (the device offers " +
+                                                  std::to_string(f->max_lds) + "); state_memory=1 forbids the "
+                                                  "global-memory form");
+        sh.lds = lds_bytes;
+        return persistent_grid(f, k_lds, nt, lds_bytes, work, &sh.grid);
+    }
+    sh.slot = (int64_t)((slot_bytes + 255) / 256 * 256);
+    TRY(persistent_grid(f, k_gmem, nt, 0, work, &sh.grid));
+    const int64_t fit = std::max<int64_t>(1, kStateScratchBudget / sh.slot);
+    sh.grid = (int)std::min<int64_t>(sh.grid, fit);
+    TRY(ensure_t(f->ws[W_GSCRATCH], sh.grid * sh.slot, s, &sh.scratch));
     return WFST_OK;
 }
 
@@ -425,46 +468,72 @@ int plan_checkpoints(wfst_fst *f, hipStream_t s, wfst_tape *t, int64_t *tiles, i
 }
 
 template <int NT>
-int launch_viterbi(const wfst_fst *f, hipStream_t s, const BatchView &bv, int2 *bp, int32_t *path_tmp,
+int launch_viterbi(const wfst_fst *fc, hipStream_t s, const BatchView &bv, int2 *bp, int32_t *path_tmp,
                    float *best_score, int32_t *best_arcs, int32_t *best_olabels)
 {
-    if (f->Q + 1 > 0xffff) return set_err(WFST_EUNSUPPORTED, "Viterbi keeps segment indices in 16 bits: num_states must be < 65535");
-    const size_t lds = lds_viterbi(f);
-    int grid = 0;
-    TRY(persistent_grid(f, viterbi_sweep<NT>, NT, lds, bv.B, &grid));
+    wfst_fst *f = const_cast<wfst_fst *>(fc);
+    SweepShape sh;
+    // on chip, segment indices are 16 bits (Q + 1 < 2^16); wider FSTs take the global form
+    TRY(sweep_shape(f, s, viterbi_sweep<NT, false>, viterbi_sweep<NT, true>, NT, lds_viterbi(f, false),
+                    lds_viterbi(f, true), f->Q + 1 > 0xffff, bv.B, sh));
     ProfScope prof(f, s, WFST_KERNEL_VITERBI);
-    hipLaunchKernelGGL((viterbi_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start,
-                       (const float *)f->final_score, bv, bp, path_tmp, best_score, best_arcs, best_olabels,
-                       (const int32_t *)f->olabel);
+    if (sh.gmem)
+        hipLaunchKernelGGL((viterbi_sweep<NT, true>), dim3(sh.grid), dim3(NT), 0, s, f->fwd, f->Q, f->start,
+                           (const float *)f->final_score, bv, bp, path_tmp, best_score, best_arcs, best_olabels,
+                           (const int32_t *)f->olabel, sh.scratch, sh.slot);
+    else
+        hipLaunchKernelGGL((viterbi_sweep<NT, false>), dim3(sh.grid), dim3(NT), sh.lds, s, f->fwd, f->Q, f->start,
+                           (const float *)f->final_score, bv, bp, path_tmp, best_score, best_arcs, best_olabels,
+                           (const int32_t *)f->olabel, nullptr, (int64_t)0);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 
 template <int NT>
-int launch_forward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
+int launch_forward(const wfst_fst *fc, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
                    float *log_z)
 {
-    const size_t lds = lds_lse(f, f->fwd);
-    int grid = 0;
-    TRY(persistent_grid(f, forward_sweep<NT>, NT, lds, bv.B, &grid));
+    wfst_fst *f = const_cast<wfst_fst *>(fc);
+    SweepShape sh;
+    const size_t bytes = lds_lse(f, f->fwd);
+    TRY(sweep_shape(f, s, forward_sweep<NT, false>, forward_sweep<NT, true>, NT, bytes, bytes, false, bv.B, sh));
     ProfScope prof(f, s, WFST_KERNEL_FORWARD);
-    hipLaunchKernelGGL((forward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start,
-                       (const float *)f->final_score, bv, tp, bk, log_z);
+    if (sh.gmem)
+        hipLaunchKernelGGL((forward_sweep<NT, true>), dim3(sh.grid), dim3(NT), 0, s, f->fwd, f->Q, f->start,
+                           (const float *)f->final_score, bv, tp, bk, log_z, sh.scratch, sh.slot);
+    else
+        hipLaunchKernelGGL((forward_sweep<NT, false>), dim3(sh.grid), dim3(NT), sh.lds, s, f->fwd, f->Q, f->start,
+                           (const float *)f->final_score, bv, tp, bk, log_z, nullptr, (int64_t)0);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 
+// The backward sweep keeps its state in global memory (and the counts take
+// the fixed-point form) when the options say so or its state exceeds LDS.
+bool backward_in_gmem(const wfst_fst *f)
+{
+    return f->state_mem == 2 || (f->state_mem == 0 && lds_backward(f) > f->max_lds);
+}
+
 template <int NT>
-int launch_backward(const wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
+int launch_backward(const wfst_fst *fc, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
                     const RecordSink &rs)
 {
-    const size_t lds = lds_backward(f);
-    int grid = 0;
-    TRY(persistent_grid(f, backward_sweep<NT>, NT, lds, bv.B, &grid));
+    wfst_fst *f = const_cast<wfst_fst *>(fc);
+    SweepShape sh;
+    const size_t bytes = lds_backward(f);
+    TRY(sweep_shape(f, s, backward_sweep<NT, false>, backward_sweep<NT, true>, NT, bytes, bytes, false, bv.B, sh));
+    if (sh.gmem && rs.key)
+        return set_err(WFST_EUNSUPPORTED, "count records need the on-chip backward sweep");
     ProfScope prof(f, s, WFST_KERNEL_BACKWARD);
-    hipLaunchKernelGGL((backward_sweep<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->rev, f->Q, f->start,
-                       (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
-                       backward_list_cap(f), rs);
+    if (sh.gmem)
+        hipLaunchKernelGGL((backward_sweep<NT, true>), dim3(sh.grid), dim3(NT), 0, s, f->fwd, f->rev, f->Q,
+                           f->start, (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
+                           backward_list_cap(f), rs, sh.scratch, sh.slot);
+    else
+        hipLaunchKernelGGL((backward_sweep<NT, false>), dim3(sh.grid), dim3(NT), sh.lds, s, f->fwd, f->rev, f->Q,
+                           f->start, (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
+                           backward_list_cap(f), rs, nullptr, (int64_t)0);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -756,7 +825,8 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
             return set_err(WFST_EINVAL, "threads_per_sentence must be 64, 128, 256, 512 or 1024");
         if (opt.checkpoint < -1 || opt.checkpoint > 2) return set_err(WFST_EINVAL, "checkpoint must be -1, 0, 1 or 2");
         if (opt.tape_budget_bytes < 0) return set_err(WFST_EINVAL, "tape_budget_bytes must be >= 0");
-        if (opt.count_records < -1) return set_err(WFST_EINVAL, "count_records must be >= -1");
+        if (opt.count_records < -2) return set_err(WFST_EINVAL, "count_records must be >= -2");
+        if (opt.state_memory < 0 || opt.state_memory > 2) return set_err(WFST_EINVAL, "state_memory must be 0, 1 or 2");
 
         hipStream_t s = as_stream(stream);
         wfst_fst *f = new wfst_fst();
@@ -767,7 +837,9 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         f->chunk = L;
         f->nt = nt;
         f->ckpt_mode = opt.checkpoint;
-        f->rec_off = opt.count_records == -1;
+        f->rec_off = opt.count_records < 0;
+        f->fx_counts = opt.count_records == -2;
+        f->state_mem = opt.state_memory;
         f->rec_max = opt.count_records > 0 ? opt.count_records : kRecordsMax;
         if (opt.tape_budget_bytes > 0) f->tape_budget = opt.tape_budget_bytes;
         if (hipGetDevice(&f->device) != hipSuccess) {
@@ -1080,12 +1152,15 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     wfst_fst *f = const_cast<wfst_fst *>(fc);
     hipStream_t s = as_stream(stream);
     if (grad_final) TRY(final_posteriors(f, tape, grad_log_z, grad_final, s));
-    if (f->A > 0) {
+    const int32_t B = tape->B;
+    const int64_t N = tape->N;
+    // expected counts by fixed-point accumulation in the backward sweep: asked
+    // for, or forced by a backward state too large for LDS
+    const bool fx = f->A > 0 && B > 0 && N > 0 && (f->fx_counts || backward_in_gmem(f));
+    if (f->A > 0 && !fx) {
         ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
         hipLaunchKernelGGL(fill_f32, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s, grad_arc_score, f->A, 0.0f);
     }
-    const int32_t B = tape->B;
-    const int64_t N = tape->N;
     if (B == 0 || N == 0) {
         HIP_OK(hipGetLastError());
         return WFST_OK;
@@ -1135,6 +1210,35 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
         }
         return WFST_OK;
     };
+    // Fixed-point counts: each posterior is added to its arc's 64-bit integer
+    // accumulator during the backward sweep; one conversion pass writes the
+    // gradient.  Integer sums do not depend on the order of the additions.
+    auto fixed_point_counts = [&]() -> int {
+        unsigned long long *acc;
+        double *scale;
+        TRY(ensure_t(f->ws[W_FXACC], f->A, s, &acc));
+        TRY(ensure_t(f->ws[W_FXSCALE], 1, s, &scale));
+        {
+            ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
+            hipLaunchKernelGGL(fill_i64, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s,
+                               reinterpret_cast<int64_t *>(acc), f->A, (int64_t)0);
+        }
+        hipLaunchKernelGGL(fx_scale_kernel, dim3(1), dim3(256), 0, s, grad_log_z, B, N, scale);
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
+        RecordSink rs;
+        rs.acc = acc;
+        rs.fx_scale = scale;
+        rs.grad_log_z = grad_log_z;
+        TRY(backward_pass(rs));
+        {
+            ProfScope prof(f, s, WFST_KERNEL_COUNTS);
+            hipLaunchKernelGGL(fx_to_grad, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s,
+                               (const unsigned long long *)acc, f->A, (const double *)scale, grad_arc_score);
+        }
+        HIP_OK(hipGetLastError());
+        return WFST_OK;
+    };
+    if (fx) return fixed_point_counts();
     bool beta_done = false;  // the beta tape of the resident-tape pass is written
     if (f->A > 0 && !f->rec_off) {
         RecordSink rs;
@@ -1152,7 +1256,10 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
             unsigned long long got[2] = {0, 0};  // slots, records
             HIP_OK(hipMemcpyAsync(got, rs.count, sizeof(got), hipMemcpyDeviceToHost, s));
             HIP_OK(hipStreamSynchronize(s));
-            if ((int64_t)got[1] > f->rec_max) break;  // too many records: grouped count kernel
+            if ((int64_t)got[1] > f->rec_max) {  // too many records: grouped count kernel, or fixed point
+                if (lds_counts(f) > f->max_lds) return fixed_point_counts();
+                break;
+            }
             if ((int64_t)got[0] <= cap) {
                 ProfScope prof(f, s, WFST_KERNEL_COUNTS);
                 uint64_t *k1;

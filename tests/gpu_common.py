@@ -99,3 +99,33 @@ def assert_final_parity(fst, batch, fst_dev, ctx=""):
     n_ok = int(np.sum(ost == oracle.ST_OK))
     assert abs(fpost.sum() - n_ok) <= 1e-5 * max(1, n_ok)
     return fpost
+
+
+def oracle_fb_parallel(fst, batch, threads=None, final_posteriors=False):
+    """oracle.forward_backward over the batch split into one part per host
+    thread (results summed over parts in part order); prints each finished
+    part.  For workloads where one serial call would run for minutes."""
+    import os
+    import threading
+    n = batch.size
+    threads = max(1, min(threads or min(os.cpu_count() or 1, 16), n))
+    cuts = [round(n * j / threads) for j in range(threads + 1)]
+    parts = [(cuts[j], cuts[j + 1]) for j in range(threads) if cuts[j + 1] > cuts[j]]
+    res = [None] * len(parts)
+
+    def run(j, lo, hi):
+        o = batch.offsets
+        sub = synth.Batch((o[lo:hi + 1] - o[lo]).copy(), batch.tokens[int(o[lo]):int(o[hi])].copy())
+        res[j] = oracle.forward_backward(fst, sub, final_posteriors=final_posteriors)
+        say(f"  oracle part {j + 1}/{len(parts)} done")
+
+    ths = [threading.Thread(target=run, args=(j, lo, hi)) for j, (lo, hi) in enumerate(parts)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    lz = np.concatenate([r[0] for r in res])
+    st = np.concatenate([r[3] for r in res])
+    post = sum(r[1] for r in res)
+    fpost = sum(r[2] for r in res) if final_posteriors else None
+    return lz, post, fpost, st

@@ -112,23 +112,32 @@ def test_bad_offsets_flagged(wf):
     assert status.tolist() == [0, 3]
 
 
-def test_too_many_states_rejected(wf):
-    # a state vector that can not live in LDS (and, for Viterbi, segment indices
-    # beyond 16 bits) is refused with WFST_EUNSUPPORTED before any sweep runs
-    say("case: 70000 states rejected")
+def test_many_states_lds_only_rejected_else_global(wf):
+    """70000 states: the state vectors do not fit LDS (and Viterbi's segment
+    indices exceed 16 bits).  With state_memory=1 (LDS only) the passes are
+    refused with WFST_EUNSUPPORTED before any sweep runs; by default they run
+    in the global-memory form and match the oracle."""
+    from gpu_common import assert_fb_parity
+    say("case: 70000 states")
     Q = 70000
-    src = np.array([0, 1, 2], np.int32)
-    dst = np.array([1, 2, Q - 1], np.int32)
-    lab = np.array([0, 0, 1], np.int32)
+    src = np.array([0, 1, 2, 0], np.int32)
+    dst = np.array([1, 2, Q - 1, 2], np.int32)
+    lab = np.array([0, 0, 1, 0], np.int32)
     fin = np.full(Q, -np.inf, np.float32)
     fin[Q - 1] = 0.0
-    d = wf.Fst(Q, 2, 0, src, dst, lab, np.zeros(3, np.float32), fin)
+    sc = np.array([-0.5, -1.0, -0.25, -2.0], np.float32)
+    d = wf.Fst(Q, 2, 0, src, dst, lab, sc, fin, state_memory=1)
     with pytest.raises(wf.WfstError) as e:
         wf.viterbi(d, np.array([0, 2], np.int32), np.array([0, 1], np.int32))
     assert e.value.code == wf.WFST_EUNSUPPORTED
     with pytest.raises(wf.WfstError) as e:
         wf.forward(d, np.array([0, 2], np.int32), np.array([0, 1], np.int32))
     assert e.value.code == wf.WFST_EUNSUPPORTED
+    fst = synth.Fst(Q, 2, 0, src, dst, lab, np.zeros(4, np.int32), sc, fin)
+    batch = synth.Batch(np.array([0, 2, 5, 5, 6], np.int64), np.array([0, 1, 0, 0, 1, 0], np.int32))
+    d = wf.Fst.from_synth(fst)
+    assert_viterbi_parity(fst, batch, d, "70000 states")
+    assert_fb_parity(fst, batch, d, "70000 states")
 
 
 def test_rejects_bad_scores(wf):
