@@ -87,32 +87,52 @@ def algorithmic_bytes(fst_dev, batch, Q=None):
     return out
 
 
-def kernel_table(prof, bytes_per, traffic=None):
-    """Per kernel: ms per launch (HIP events on the call stream), the method's
-    bytes per launch, their rate and its fraction of the HBM peak; measured
-    HBM bytes per launch from the committed counter summary when current."""
+def kernel_table(prof, bytes_per, steps, traffic=None, fused_counts=False):
+    """Per kernel kind: ms per pass over the batch (HIP events on the call
+    stream, summed over the pass's launches), the method's bytes per pass,
+    their rate and its fraction of the HBM peak; measured HBM bytes per pass
+    from the committed counter summary when it is current.
+    A checkpointed backward pass is one launch per block of steps and comes
+    with a second forward pass (the blocks' recompute); with fused_counts the
+    expected counts are taken inside the backward sweep, whose row then
+    carries the count bytes too (the counts row is the conversion pass)."""
+    launches = {k: n for k, (ms, n) in prof.items()}
+    blocks = max(1, round(launches.get("backward", 0) / max(steps, 1)))
+    passes = {k: n / max(steps, 1) for k, n in launches.items()}
+    if blocks > 1:
+        passes["backward"] = 1
+        passes["forward"] = 2
+    by = dict(bytes_per)
+    if fused_counts:
+        by["backward"] = by["backward"] + by["counts"]
+        by["counts"] = 0.0
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:
             continue
-        avg = ms / n
-        gbs = bytes_per[k] / (avg * 1e-3) / 1e9
-        row = {"ms_per_launch": round(avg, 4), "launches": n, "alg_bytes_per_launch": bytes_per[k],
+        npass = passes[k] * steps
+        avg = ms / npass
+        gbs = by[k] / (avg * 1e-3) / 1e9
+        row = {"ms_per_pass": round(avg, 4), "passes": npass, "launches": n, "alg_bytes_per_pass": by[k],
                "alg_GBps": round(gbs, 1), "alg_frac": round(gbs / PEAK_HBM_GBS, 4)}
         t = (traffic or {}).get(k)
         if t:
-            row["dram_bytes_per_launch"] = t
+            row["dram_bytes_per_pass"] = t
             row["dram_GBps"] = round(t / (avg * 1e-3) / 1e9, 1)
         kernels[k] = row
     return kernels
 
 
-def roofline_of(kernels, traffic_total=None):
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"] * kernels[k]["launches"])
+def step_bytes(kernels, steps):
+    return sum(v["alg_bytes_per_pass"] * v["passes"] for v in kernels.values()) / max(steps, 1)
+
+
+def roofline_of(kernels):
+    """The kernel kind with the most time per step, its rate and its fraction of peak."""
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_pass"] * kernels[k]["passes"])
     dk = kernels[dom]
     return {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(dk["alg_GBps"] / PEAK_HBM_GBS, 4),
-            "traffic": dk.get("dram_bytes_per_launch")}
+            "frac": round(dk["alg_GBps"] / PEAK_HBM_GBS, 4), "traffic": dk.get("dram_bytes_per_pass")}
 
 
 def load_traffic(name="traffic_trigram_4096.json"):
@@ -125,7 +145,7 @@ def load_traffic(name="traffic_trigram_4096.json"):
         t = json.load(f)
     if t.get("source_sha") != source_sha():
         return None
-    return {k: v.get("bytes_per_launch") for k, v in t.get("kernels", {}).items()}
+    return {k: v.get("bytes_per_pass", v.get("bytes_per_launch")) for k, v in t.get("kernels", {}).items()}
 
 
 def _sub_batch(batch, lo, hi):
@@ -338,7 +358,7 @@ def main():
     ms_step, prof = time_steps(step, args.steps, args.warmup, d)
     health = d.health()
     traffic = load_traffic()
-    kernels = kernel_table(prof, algorithmic_bytes(d, batch), traffic)
+    kernels = kernel_table(prof, algorithmic_bytes(d, batch), args.steps, traffic)
     roofline = roofline_of(kernels)
     copy_gbs = copy_bandwidth(dev)
     roofline["copy_GBps"] = round(copy_gbs, 1)
@@ -362,9 +382,9 @@ def main():
             lz, _ = wf.log_partition(th3, d, off3, tok3)
             lz.sum().backward()
         ms3, prof3 = time_steps(train_step, args.steps, args.warmup, d)
-        k3 = kernel_table(prof3, algorithmic_bytes(d, b3))
+        k3 = kernel_table(prof3, algorithmic_bytes(d, b3), args.steps)
         n3 = int(b3.offsets[-1])
-        total_alg = sum(v["alg_bytes_per_launch"] * v["launches"] for v in k3.values()) / args.steps
+        total_alg = step_bytes(k3, args.steps)
         training = {"workload": f"trigram tagger WFST ({fst.num_arcs} arcs), {b3.size} sentences, {n3} symbols "
                                 "(lognormal lengths mean 25 in [5,60]); loss = sum of log Z; "
                                 "step = set_scores + forward + backward with expected counts through "
@@ -384,7 +404,7 @@ def main():
         chosen4, times4 = d4.autotune(off4, tok4)
         log(f"  autotune: {chosen4} threads per sentence; ms per pass {times4}")
         rates4, prof4 = batched_rates(wf, d4, b4, off4, tok4, args.steps, args.warmup)
-        k4 = kernel_table(prof4, algorithmic_bytes(d4, b4))
+        k4 = kernel_table(prof4, algorithmic_bytes(d4, b4), args.steps)
         P4 = min(max(args.per_sentence, 1), b4.size)
         log(f"  per-sentence form on {P4} sentences")
         ps4 = per_sentence_rates(wf, d4, b4, off4, tok4, P4)
@@ -416,9 +436,10 @@ def main():
             lz, _ = wf.log_partition(th5, d5, off5, tok5)
             lz.sum().backward()
         ms5, prof5 = time_steps(train5, args.powerlaw_steps, 1, d5)
-        k5 = kernel_table(prof5, algorithmic_bytes(d5, b5, Q=f5.num_states))
+        k5 = kernel_table(prof5, algorithmic_bytes(d5, b5, Q=f5.num_states), args.powerlaw_steps,
+                          fused_counts=True)
         n5 = int(b5.offsets[-1])
-        total5 = sum(v["alg_bytes_per_launch"] * v["launches"] for v in k5.values()) / args.powerlaw_steps
+        total5 = step_bytes(k5, args.powerlaw_steps)
         powerlaw = {"workload": f"power-law WFST: {f5.num_states} states, {f5.num_arcs} arcs, out-degree "
                                 "~d^-2.1 on [10,5000], labels Zipf(1.0) over 10k, scores -Exp(1); "
                                 f"{b5.size} random-walk strings of 100 ({n5} symbols); CRF training step = "
@@ -472,7 +493,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
-        "batched_viterbi_symbols_per_s": round(n_sym / (kernels["viterbi"]["ms_per_launch"] * 1e-3), 1),
+        "batched_viterbi_symbols_per_s": round(n_sym / (kernels["viterbi"]["ms_per_pass"] * 1e-3), 1),
         "per_sentence": per_sentence,
         "training_1024": training,
         "bigram_16384": bigram,
