@@ -190,6 +190,27 @@ int wfst_viterbi(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const i
                  int32_t *best_olabels, int32_t *status, void *stream);
 
 /*
+ * wfst_viterbi for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, outputs and results (bit for bit) as wfst_viterbi, but no
+ * allocation of any kind and no host read-back.  Its scratch (queue counter,
+ * sentence order, per-token offsets, scan tiles, back-pointers, path) lives in
+ * one 256 MiB array per GPU, held until the process ends.  Limits:
+ *   - num_tokens * (largest number of destination segments of one label)
+ *     * 8 bytes, plus about 16 bytes per token and 4 per sentence, must fit
+ *     256 MiB, else WFST_EUNSUPPORTED (before any work is queued);
+ *   - only the on-chip form (state vectors in LDS): an FST that needs the
+ *     global-memory form gives WFST_EUNSUPPORTED;
+ *   - the FST's device must be the current device (else WFST_EINVAL).
+ * Every call on one GPU uses the same scratch: calls that overlap on one GPU
+ * (other streams, other threads, other FSTs) race and must be serialised by
+ * the caller.
+ */
+int wfst_viterbi_noalloc(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                         const int32_t *tokens, float *best_score, int32_t *best_arcs,
+                         int32_t *best_olabels, int32_t *status, void *stream);
+
+/*
  * Forward pass (paper, Algorithm 2 first loop, log semiring): log_z float[batch]
  * (DEVICE), status int32[batch] (DEVICE).  *tape_out receives a library-owned
  * record of the pass for wfst_backward; free it with wfst_tape_free.  The tape

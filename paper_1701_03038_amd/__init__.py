@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "WfstError", "Fst", "Tape", "viterbi", "forward", "backward", "forward_backward",
+    "WfstError", "Fst", "Tape", "viterbi", "viterbi_noalloc", "forward", "backward", "forward_backward",
     "LogPartition", "log_partition", "load_library", "layout_host", "library_path",
     "STATUS_OK", "STATUS_NO_PATH", "STATUS_BAD_TOKEN", "STATUS_BAD_INPUT",
 ]
@@ -63,7 +63,7 @@ EXPORTS = (
     "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats",
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
-    "wfst_fst_score_version",
+    "wfst_fst_score_version", "wfst_viterbi_noalloc",
 )
 
 
@@ -88,6 +88,7 @@ def load_library(path: str | None = None):
     lib.wfst_fst_label_stats.argtypes = [P, P, P, P]
     lib.wfst_fst_profile_read.argtypes = [P, P, P, i32]
     lib.wfst_viterbi.argtypes = [P, i32, i64, P, P, P, P, P, P, P]
+    lib.wfst_viterbi_noalloc.argtypes = [P, i32, i64, P, P, P, P, P, P, P]
     lib.wfst_forward.argtypes = [P, i32, i64, P, P, P, P, ctypes.POINTER(P), P]
     lib.wfst_backward.argtypes = [P, P, P, P, P, P]
     lib.wfst_tape_free.argtypes = [P]
@@ -100,7 +101,7 @@ def load_library(path: str | None = None):
     lib.wfst_fst_score_version.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
     for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health",
                  "wfst_fst_score_version", "wfst_fst_profile", "wfst_fst_profile_read",
-                 "wfst_fst_label_stats", "wfst_viterbi",
+                 "wfst_fst_label_stats", "wfst_viterbi", "wfst_viterbi_noalloc",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
                  "wfst_fst_autotune"):
         getattr(lib, name).restype = ctypes.c_int
@@ -285,6 +286,25 @@ def viterbi(fst: Fst, offsets, tokens, olabels: bool = False):
     _check(_lib.wfst_viterbi(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(score), _dptr(arcs),
                              _dptr(ol), _dptr(status), _stream()))
     return (score, arcs, status, ol) if olabels else (score, arcs, status)
+
+
+def viterbi_noalloc(fst: Fst, offsets, tokens, out=None, olabels: bool = False):
+    """viterbi() through the entry point that allocates nothing (its scratch is
+    one fixed array per GPU).  `out` may pass preallocated (score f32[B],
+    arcs i32[N], status i32[B][, olabels i32[N]]) device tensors."""
+    import torch
+    off, tok, B, N = _batch(offsets, tokens)
+    dev = off.device
+    if out is None:
+        out = (torch.empty(B, dtype=torch.float32, device=dev), torch.empty(N, dtype=torch.int32, device=dev),
+               torch.empty(B, dtype=torch.int32, device=dev))
+        if olabels:
+            out = out + (torch.empty(N, dtype=torch.int32, device=dev),)
+    score, arcs, status = out[:3]
+    ol = out[3] if len(out) > 3 else None
+    _check(_lib.wfst_viterbi_noalloc(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(score), _dptr(arcs),
+                                     _dptr(ol), _dptr(status), _stream()))
+    return out
 
 
 class Tape:

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -235,7 +236,7 @@ struct ProfScope {
     bool on = false;
     ProfScope(const wfst_fst *fc, hipStream_t st, int k) : f(const_cast<wfst_fst *>(fc)), s(st), kind(k)
     {
-        if (!f->prof) return;
+        if (!f->prof || k < 0) return;
         if (!f->spare.empty()) {
             m = f->spare.back();
             f->spare.pop_back();
@@ -469,14 +470,23 @@ int plan_checkpoints(wfst_fst *f, hipStream_t s, wfst_tape *t, int64_t *tiles, i
 
 template <int NT>
 int launch_viterbi(const wfst_fst *fc, hipStream_t s, const BatchView &bv, int2 *bp, int32_t *path_tmp,
-                   float *best_score, int32_t *best_arcs, int32_t *best_olabels)
+                   float *best_score, int32_t *best_arcs, int32_t *best_olabels, bool no_alloc = false)
 {
     wfst_fst *f = const_cast<wfst_fst *>(fc);
     SweepShape sh;
     // on chip, segment indices are 16 bits (Q + 1 < 2^16); wider FSTs take the global form
-    TRY(sweep_shape(f, s, viterbi_sweep<NT, false>, viterbi_sweep<NT, true>, NT, lds_viterbi(f, false),
-                    lds_viterbi(f, true), f->Q + 1 > 0xffff, bv.B, sh));
-    ProfScope prof(f, s, WFST_KERNEL_VITERBI);
+    const bool wide = f->Q + 1 > 0xffff;
+    if (no_alloc) {  // on-chip form only: its grid needs no memory beyond the caller's scratch
+        if (wide || f->state_mem == 2 || lds_viterbi(f, false) > f->max_lds)
+            return set_err(WFST_EUNSUPPORTED, "the no-allocation Viterbi runs only the on-chip form "
+                                              "(state vectors in LDS); this FST needs the global-memory form");
+        sh.lds = lds_viterbi(f, false);
+        TRY(persistent_grid(f, viterbi_sweep<NT, false>, NT, sh.lds, bv.B, &sh.grid));
+    } else {
+        TRY(sweep_shape(f, s, viterbi_sweep<NT, false>, viterbi_sweep<NT, true>, NT, lds_viterbi(f, false),
+                        lds_viterbi(f, true), wide, bv.B, sh));
+    }
+    ProfScope prof(f, s, no_alloc ? -1 : WFST_KERNEL_VITERBI);
     if (sh.gmem)
         hipLaunchKernelGGL((viterbi_sweep<NT, true>), dim3(sh.grid), dim3(NT), 0, s, f->fwd, f->Q, f->start,
                            (const float *)f->final_score, bv, bp, path_tmp, best_score, best_arcs, best_olabels,
@@ -727,6 +737,37 @@ int reduce_records(wfst_fst *f, hipStream_t s, int64_t n, int64_t N, uint64_t *k
 }
 
 constexpr int64_t kRecordsMax = (int64_t)1 << 28;  // records per call before the grouped count kernel is used
+
+}  // namespace
+
+// Scratch of wfst_viterbi_noalloc: one array per GPU, held until the process
+// ends; every call on a GPU reuses (and overwrites) that GPU's copy.  Host
+// code never passes the array's name to a kernel: it is only a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, per device.
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<unsigned char *> g_scratch_ptr;  // device address of `scratch`, per device (null: not looked up)
+
+// The current device's address of `scratch` (looked up once per device, with
+// that device current).
+int static_scratch(int dev, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[(size_t)dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_err(WFST_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[(size_t)dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[(size_t)dev];
+    return WFST_OK;
+}
 
 }  // namespace
 
@@ -1066,6 +1107,61 @@ int wfst_viterbi(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const in
     const BatchView bv = make_view(f, batch, N, offsets, tokens, order, tok_off, counters + C_QUEUE, status);
     int rc;
     DISPATCH_NT(rc, f->nt, launch_viterbi, f, s, bv, bp, path_tmp, best_score, best_arcs, best_olabels)
+    return rc;
+}
+
+int wfst_viterbi_noalloc(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                         const int32_t *tokens, float *best_score, int32_t *best_arcs, int32_t *best_olabels,
+                         int32_t *status, void *stream)
+{
+    TRY(check_batch(fc, batch, num_tokens, offsets, tokens));
+    if (batch == 0) return WFST_OK;
+    if (!best_score || !status || (num_tokens > 0 && !best_arcs)) return set_err(WFST_EINVAL, "NULL output");
+    if (best_olabels && !fc->olabel) return set_err(WFST_EINVAL, "FST was created without olabels");
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != fc->device) return set_err(WFST_EINVAL, "the FST's device must be the current device");
+    unsigned char *base = nullptr;
+    TRY(static_scratch(dev, &base));
+    hipStream_t s = as_stream(stream);
+    const int64_t N = num_tokens;
+    // carve the scratch: counters | order | tok_off | scan tiles | path | back-pointers (bound: N x max segments)
+    const int64_t segs = std::max(fc->fwd.max_segs, 1);
+    size_t at = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t here = at;
+        at += (bytes + 255) / 256 * 256;
+        return here;
+    };
+    const size_t o_cnt = carve(C_COUNT * sizeof(int32_t));
+    const size_t o_order = carve((size_t)batch * sizeof(int32_t));
+    const size_t o_tok = carve((size_t)std::max<int64_t>(N, 1) * sizeof(int64_t));
+    const size_t o_tiles = carve((size_t)scan_tiles_for(N) * sizeof(int64_t));
+    const size_t o_path = carve((size_t)std::max<int64_t>(N, 1) * sizeof(int32_t));
+    if ((double)N * (double)segs * sizeof(int2) > (double)kStaticScratchBytes)
+        return set_err(WFST_EUNSUPPORTED, "batch too large for the no-allocation Viterbi: " + std::to_string(N) +
+                                              " tokens x " + std::to_string(segs) +
+                                              " segments per label need more than its " +
+                                              std::to_string(kStaticScratchBytes >> 20) + " MiB of scratch");
+    const size_t o_bp = carve((size_t)N * (size_t)segs * sizeof(int2));
+    if (at > kStaticScratchBytes)
+        return set_err(WFST_EUNSUPPORTED, "batch too large for the no-allocation Viterbi: needs " +
+                                              std::to_string(at) + " bytes of its " +
+                                              std::to_string(kStaticScratchBytes) + "-byte scratch");
+    int32_t *counters = reinterpret_cast<int32_t *>(base + o_cnt);
+    int32_t *order = reinterpret_cast<int32_t *>(base + o_order);
+    int64_t *tok_off = reinterpret_cast<int64_t *>(base + o_tok);
+    int64_t *tiles = reinterpret_cast<int64_t *>(base + o_tiles);
+    int32_t *path_tmp = reinterpret_cast<int32_t *>(base + o_path);
+    int2 *bp = reinterpret_cast<int2 *>(base + o_bp);
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
+    Plan p;
+    // the bound N x max segments always fits here, so the plan reads nothing back
+    TRY(make_plan(fc, s, batch, N, offsets, tokens, order, tok_off, tiles,
+                  reinterpret_cast<int64_t *>(counters + C_TOTAL), INT64_MAX, p));
+    const BatchView bv = make_view(fc, batch, N, offsets, tokens, order, tok_off, counters + C_QUEUE, status);
+    int rc;
+    DISPATCH_NT(rc, fc->nt, launch_viterbi, fc, s, bv, bp, path_tmp, best_score, best_arcs, best_olabels, true)
     return rc;
 }
 
