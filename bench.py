@@ -297,7 +297,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the multi-threaded oracle timing (0: the host's CPUs, at most 16)")
     ap.add_argument("--autotune", action="store_true",
-                    help="pick the workgroup size per sentence with wfst_fst_autotune on this batch (untimed)")
+                    help="pick workgroup size and count path with wfst_fst_autotune on this batch (untimed)")
     ap.add_argument("--threads", type=int, default=0,
                     help="workgroup size per sentence of the sweeps (64..1024; 0: library default)")
     ap.add_argument("--powerlaw-steps", type=int, default=2,
@@ -343,9 +343,10 @@ def main():
     tuned = None
     if args.autotune:
         d.set_scores(theta)
-        chosen, times = d.autotune(off, tok)
-        tuned = {"threads_per_sentence": chosen, "ms_per_pass": times}
-        log(f"autotune: {chosen} threads per sentence; ms per pass {times}")
+        tuned = d.autotune(off, tok)
+        log(f"autotune: {tuned['threads_per_sentence']} threads per sentence, {tuned['count_path']} counts; "
+            f"{tuned['best_ms']} ms per pass")
+        tuned = {k: v for k, v in tuned.items() if k != "times"}
 
     def step():
         d.set_scores(theta)
@@ -401,8 +402,10 @@ def main():
         f4, b4 = synth.config(4)
         d4 = wf.Fst.from_synth(f4)
         off4, tok4 = to_dev(b4)
-        chosen4, times4 = d4.autotune(off4, tok4)
-        log(f"  autotune: {chosen4} threads per sentence; ms per pass {times4}")
+        tune4 = d4.autotune(off4, tok4, tune_chunk=True)
+        log(f"  autotune: chunk {tune4['chunk_arcs']}, {tune4['threads_per_sentence']} threads per sentence, "
+            f"{tune4['count_path']} counts; {tune4['best_ms']} ms per pass ({tune4['tried']} timed)")
+        tune4 = {k: v for k, v in tune4.items() if k != "times"}
         rates4, prof4 = batched_rates(wf, d4, b4, off4, tok4, args.steps, args.warmup)
         k4 = kernel_table(prof4, algorithmic_bytes(d4, b4), args.steps)
         P4 = min(max(args.per_sentence, 1), b4.size)
@@ -410,7 +413,7 @@ def main():
         ps4 = per_sentence_rates(wf, d4, b4, off4, tok4, P4)
         bigram = {"workload": f"bigram tagger WFST: 45 tags, 46 states, vocab 200000, {f4.num_arcs} arcs; "
                               f"{b4.size} sentences, {int(b4.offsets[-1])} symbols (lengths uniform 1..200)",
-                  "autotune": {"threads_per_sentence": chosen4, "ms_per_pass": times4},
+                  "autotune": tune4,
                   "batched": rates4, "per_sentence": ps4,
                   "batched_over_per_sentence": {
                       "viterbi": round(rates4["viterbi_symbols_per_s"] / ps4["viterbi_symbols_per_s"], 1),
@@ -489,7 +492,8 @@ def main():
                    "step": "set_scores + batched Viterbi with backtrace + batched forward (log Z) + "
                            "batched backward with expected counts over all arcs",
                    "parallelism": "single GPU",
-                   "threads_per_sentence": tuned["threads_per_sentence"] if tuned else (args.threads or 256)},
+                   "threads_per_sentence": tuned["threads_per_sentence"] if tuned else (args.threads or 256),
+                   "autotune": tuned},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -254,23 +254,50 @@ int wfst_forward_backward(const wfst_fst *fst, int32_t batch, int64_t num_tokens
 
 /*
  * Autotuner for batched decoding and training (the batching step of the
- * method: one persistent workgroup per sentence at a time).  Times one batched
- * Viterbi + forward + backward pass on the given batch (offsets/tokens as in
- * wfst_viterbi, DEVICE) for each workgroup size per sentence in
- * {64, 128, 256, 512, 1024}, after one untimed pass per size, and keeps the
- * fastest for later calls on this FST (as if it had been created with that
- * threads_per_sentence).  Results of every call stay exact for every size
- * (Viterbi bit-exact, forward-backward within its stated accuracy); only
- * speed changes.
- *   threads_out: HOST int32 or NULL, receives the chosen size.
- *   times_ms: HOST float[5] or NULL, milliseconds per pass for each size in
- *     the order above; -1 for a size the FST's LDS needs do not allow.
- * Allocates and frees its own scratch outputs (one float per arc among them)
- * and synchronises the stream: call it off the hot path.  On error the FST
- * keeps its previous size.
+ * method: persistent workgroups popping sentences longest first; section 5
+ * launches one kernel per symbol, and section 7.5 reports that its launch
+ * overhead dominated small FSTs, which is why every launch parameter here is
+ * measured rather than fixed).  On the given batch (offsets/tokens DEVICE, as
+ * in wfst_viterbi) it times one batched Viterbi + forward + backward pass,
+ * after one untimed pass, for each
+ *   - workgroup size per sentence in {64, 128, 256, 512, 1024},
+ *   - count path: 0 per-visit records, -1 label-grouped kernel, -2 fixed-point
+ *     accumulation (those the FST's state sizes allow), and
+ *   - with flags & WFST_TUNE_CHUNK: arcs per lane chunk in {4, 8, 16, 32},
+ *     rebuilding both layouts from the device layout for each (arcs and their
+ *     current scores are read back; the FST keeps no host copy),
+ * and keeps the fastest for later calls on this FST.  Sentences are always
+ * processed longest first in exact-length order (the finest length buckets),
+ * so there are no bucket edges to tune.  Results of every configuration stay
+ * exact (Viterbi bit-exact, forward-backward within its stated accuracy); only
+ * speed changes.  A rebuild makes earlier tapes of the FST unusable
+ * (wfst_backward refuses them).
+ *   cache_path: NULL, or a JSON file of earlier choices keyed by device
+ *     architecture, FST size (states, labels, arcs) and batch shape
+ *     (sentences, tokens, mean arcs per token, log2 histogram of lengths); a
+ *     hit applies the stored choice without timing, a miss tunes and adds the
+ *     entry (the file is rewritten through a temporary file).
+ *   result: HOST, or NULL.
+ * Allocates and frees scratch outputs (one float per arc among them) and
+ * synchronises the stream: call it off the hot path.  On error the FST keeps
+ * its previous configuration.
  */
+#define WFST_TUNE_CHUNK 1
+
+typedef struct wfst_autotune_result {
+    int32_t threads_per_sentence;  /* chosen configuration */
+    int32_t count_records;         /* chosen count path (0, -1 or -2, as wfst_options.count_records) */
+    int32_t chunk_arcs;
+    int32_t from_cache;            /* 1: taken from the cache file, nothing timed */
+    int32_t tried;                 /* configurations timed */
+    float best_ms;                 /* ms of one pass with the chosen configuration (as timed or stored) */
+    int32_t chunks[4];             /* chunk length of each row of ms (0 = row unused) */
+    float ms[4][5][3];             /* ms per pass [chunk row][workgroup size][count path]; -1 = not run */
+} wfst_autotune_result;
+
 int wfst_fst_autotune(wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
-                      const int32_t *tokens, int32_t *threads_out, float *times_ms, void *stream);
+                      const int32_t *tokens, const char *cache_path, int32_t flags,
+                      wfst_autotune_result *result, void *stream);
 
 /* Message for the last nonzero return on this thread ("" if none). */
 const char *wfst_last_error(void);

@@ -58,6 +58,17 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64)]
 
 
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("threads_per_sentence", ctypes.c_int32), ("count_records", ctypes.c_int32),
+                ("chunk_arcs", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("tried", ctypes.c_int32),
+                ("best_ms", ctypes.c_float), ("chunks", ctypes.c_int32 * 4),
+                ("ms", ((ctypes.c_float * 3) * 5) * 4)]
+
+
+TUNE_CHUNK = 1
+THREAD_SIZES = (64, 128, 256, 512, 1024)
+COUNT_PATHS = {0: "records", -1: "grouped", -2: "fixed_point"}
+
 EXPORTS = (
     "wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_destroy", "wfst_fst_get_info", "wfst_fst_health",
     "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats",
@@ -97,7 +108,7 @@ def load_library(path: str | None = None):
     lib.wfst_last_error.argtypes = []
     lib.wfst_last_error.restype = ctypes.c_char_p
     lib.wfst_layout_host.argtypes = [i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
-    lib.wfst_fst_autotune.argtypes = [P, i32, i64, P, P, ctypes.POINTER(i32), P, P]
+    lib.wfst_fst_autotune.argtypes = [P, i32, i64, P, P, ctypes.c_char_p, i32, ctypes.POINTER(_TuneResult), P]
     lib.wfst_fst_score_version.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
     for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health",
                  "wfst_fst_score_version", "wfst_fst_profile", "wfst_fst_profile_read",
@@ -226,16 +237,28 @@ class Fst:
                 raise WfstError(WFST_EINVAL, "scores must be contiguous float32 device tensors")
         _check(_lib.wfst_fst_set_scores(self.handle, _dptr(arc_score), _dptr(final_score), _stream()))
 
-    def autotune(self, offsets, tokens):
-        """Time batched Viterbi + forward + backward on this batch for each workgroup size
-        per sentence and keep the fastest; returns (size, {size: ms or None if it does not fit})."""
+    def autotune(self, offsets, tokens, cache_path=None, tune_chunk=False):
+        """Time batched Viterbi + forward + backward on this batch for every
+        workgroup size per sentence, count path and (tune_chunk) chunk length,
+        keep the fastest; cache_path: JSON file of earlier choices.  Returns a
+        dict with the choice and the timings {(chunk, threads, count path): ms}."""
         off, tok, B, N = _batch(offsets, tokens)
-        chosen = ctypes.c_int32(0)
-        ms = np.zeros(5, np.float32)
-        _check(_lib.wfst_fst_autotune(self.handle, B, N, _dptr(off), _dptr(tok), ctypes.byref(chosen),
-                                      _np_ptr(ms), _stream()))
-        return int(chosen.value), {n: (float(t) if t >= 0 else None)
-                                   for n, t in zip((64, 128, 256, 512, 1024), ms)}
+        r = _TuneResult()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(_lib.wfst_fst_autotune(self.handle, B, N, _dptr(off), _dptr(tok), path,
+                                      TUNE_CHUNK if tune_chunk else 0, ctypes.byref(r), _stream()))
+        times = {}
+        for c in range(4):
+            if r.chunks[c] == 0:
+                continue
+            for k, nt in enumerate(THREAD_SIZES):
+                for m, mode in enumerate((0, -1, -2)):
+                    v = r.ms[c][k][m]
+                    if v >= 0:
+                        times[(int(r.chunks[c]), nt, COUNT_PATHS[mode])] = round(float(v), 4)
+        return {"threads_per_sentence": r.threads_per_sentence, "count_path": COUNT_PATHS[r.count_records],
+                "chunk_arcs": r.chunk_arcs, "from_cache": bool(r.from_cache), "tried": r.tried,
+                "best_ms": round(float(r.best_ms), 4), "times": times}
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -10,8 +10,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -132,7 +135,7 @@ struct wfst_fst {
     int64_t bytes = 0;
     int cu_count = 0;
     size_t max_lds = 0;
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, size_t>> allocs;  // owned device arrays and their bytes
     Buf ws[W_NUM];
     std::vector<TapeBufs *> tape_pool;
     // per-kernel timing (wfst_fst_profile): event pairs recorded around the main kernels
@@ -172,7 +175,7 @@ int dev_upload(wfst_fst *f, T **dst, const T *src, int64_t count, hipStream_t s)
     const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
     void *p = nullptr;
     HIP_OK(hipMalloc(&p, bytes));
-    f->allocs.push_back(p);
+    f->allocs.emplace_back(p, bytes);
     f->bytes += (int64_t)bytes;
     if (src && count > 0) HIP_OK(hipMemcpyAsync(p, src, (size_t)count * sizeof(T), hipMemcpyHostToDevice, s));
     *dst = reinterpret_cast<T *>(p);
@@ -199,6 +202,27 @@ int upload_layout(wfst_fst *f, const HostLayout &h, DevLayout &d, hipStream_t s)
     return WFST_OK;
 }
 
+// Free one device array owned by the FST (nullptr-safe).
+void free_owned(wfst_fst *f, void *p)
+{
+    if (!p) return;
+    for (size_t i = 0; i < f->allocs.size(); ++i)
+        if (f->allocs[i].first == p) {
+            f->bytes -= (int64_t)f->allocs[i].second;
+            f->allocs.erase(f->allocs.begin() + (ptrdiff_t)i);
+            break;
+        }
+    (void)hipFree(p);
+}
+
+void free_layout(wfst_fst *f, DevLayout &d)
+{
+    for (void *p : {(void *)d.other, (void *)d.score, (void *)d.elem_arc, (void *)d.slice, (void *)d.seg_key,
+                    (void *)d.seg_chunk, (void *)d.label})
+        free_owned(f, p);
+    d = DevLayout();
+}
+
 void free_buf(Buf &b)
 {
     if (b.p) (void)hipFree(b.p);
@@ -213,7 +237,7 @@ void free_fst(wfst_fst *f)
     const bool other = hipGetDevice(&cur) == hipSuccess && cur != f->device;
     if (other) (void)hipSetDevice(f->device);
     (void)hipDeviceSynchronize();
-    for (void *p : f->allocs) (void)hipFree(p);
+    for (auto &a : f->allocs) (void)hipFree(a.first);
     for (Buf &b : f->ws) free_buf(b);
     for (TapeBufs *t : f->tape_pool) {
         for (Buf *b : {&t->order, &t->tok_off, &t->alpha, &t->a_max, &t->a_log, &t->log_z, &t->tiles, &t->total,
@@ -766,6 +790,169 @@ int static_scratch(int dev, unsigned char **out)
         g_scratch_ptr[(size_t)dev] = static_cast<unsigned char *>(p);
     }
     *out = g_scratch_ptr[(size_t)dev];
+    return WFST_OK;
+}
+
+// Count path of later calls: 0 records (with fallbacks), -1 label-grouped
+// kernel, -2 fixed-point accumulation.
+void set_count_mode(wfst_fst *f, int32_t mode)
+{
+    f->rec_off = mode < 0;
+    f->fx_counts = mode == -2;
+}
+
+int32_t count_mode(const wfst_fst *f) { return f->fx_counts ? -2 : (f->rec_off ? -1 : 0); }
+
+// Rebuild both layouts with another chunk length.  The arcs (label, source,
+// destination, id) and their current scores are read back from the forward
+// layout, so the FST keeps no host copy of its arcs.  Synchronises the stream.
+int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
+{
+    if (chunk == f->chunk) return WFST_OK;
+    if (chunk < 1 || chunk > 64) return set_err(WFST_EINVAL, "chunk_arcs must be in [1, 64]");
+    const DevLayout &d = f->fwd;
+    HIP_OK(hipStreamSynchronize(s));
+    std::vector<int32_t> other((size_t)d.n_elem), earc((size_t)d.n_elem), seg_key((size_t)d.n_seg);
+    std::vector<float> score((size_t)d.n_elem);
+    std::vector<SliceInfo> slice((size_t)d.n_slice);
+    std::vector<SegChunk> seg_chunk((size_t)d.n_seg);
+    std::vector<LabelInfo> label((size_t)f->M);
+    HIP_OK(hipMemcpy(other.data(), d.other, other.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(earc.data(), d.elem_arc, earc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(score.data(), d.score, score.size() * sizeof(float), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(seg_key.data(), d.seg_key, seg_key.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(slice.data(), d.slice, slice.size() * sizeof(SliceInfo), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(seg_chunk.data(), d.seg_chunk, seg_chunk.size() * sizeof(SegChunk), hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(label.data(), d.label, label.size() * sizeof(LabelInfo), hipMemcpyDeviceToHost));
+    // arcs in id order: the forward layout's slot (row r, lane l) of slice s holds
+    // chunk s*64 + l of its label, whose segment's key is the destination
+    std::vector<int32_t> src((size_t)f->A, 0), dst((size_t)f->A, 0), ilabel((size_t)f->A, 0);
+    std::vector<float> sc((size_t)f->A, 0.0f);
+    std::vector<int32_t> chunk_seg;
+    for (int32_t a = 0; a < f->M; ++a) {
+        const LabelInfo &li = label[(size_t)a];
+        chunk_seg.assign((size_t)std::max(li.n_slots, 1), 0);
+        for (int32_t j = 0; j < li.n_multi; ++j) {
+            const SegChunk &c = seg_chunk[(size_t)(li.seg_first + j)];
+            for (int32_t p = 0; p < c.count; ++p) chunk_seg[(size_t)(c.first + p)] = j;
+        }
+        for (int32_t sl = 0; sl < li.n_slices; ++sl) {
+            const SliceInfo &si = slice[(size_t)(li.slice_first + sl)];
+            for (int32_t l = 0; l < si.width; ++l) {
+                const int32_t c = sl * 64 + l;
+                const int32_t j = c < li.n_slots ? chunk_seg[(size_t)c] : li.n_multi + (c - li.n_slots);
+                const int32_t key = seg_key[(size_t)(li.seg_first + j)];
+                for (int32_t r = 0; r < si.height; ++r) {
+                    const int64_t e = (int64_t)si.base + (int64_t)r * si.width + l;
+                    const int32_t k = earc[(size_t)e];
+                    if (k < 0) continue;
+                    src[(size_t)k] = other[(size_t)e];
+                    dst[(size_t)k] = key;
+                    ilabel[(size_t)k] = a;
+                    sc[(size_t)k] = score[(size_t)e];
+                }
+            }
+        }
+    }
+    std::vector<int32_t>().swap(other);
+    std::vector<int32_t>().swap(earc);
+    std::vector<float>().swap(score);
+    std::string err;
+    HostLayout hf, hr;
+    int rc = build_layout(f->Q, f->M, f->A, src.data(), dst.data(), ilabel.data(), sc.data(), 0, chunk, hf, err);
+    if (rc == WFST_OK)
+        rc = build_layout(f->Q, f->M, f->A, src.data(), dst.data(), ilabel.data(), sc.data(), 1, chunk, hr, err);
+    if (rc != WFST_OK) return set_err(rc, err);
+    free_layout(f, f->fwd);
+    free_layout(f, f->rev);
+    TRY(upload_layout(f, hf, f->fwd, s));
+    TRY(upload_layout(f, hr, f->rev, s));
+    HIP_OK(hipStreamSynchronize(s));
+    f->chunk = chunk;
+    f->score_version += 1;  // tapes made on the old layouts are not used again
+    return WFST_OK;
+}
+
+// Autotune cache: one JSON object, one entry per line,
+//   "key": {"threads_per_sentence": 64, "count_records": -2, "chunk_arcs": 16, "ms": 4.5},
+struct TuneEntry {
+    int32_t nt = 0, mode = 0, chunk = 0;
+    float ms = -1.0f;
+};
+
+std::vector<std::pair<std::string, TuneEntry>> read_tune_cache(const char *path)
+{
+    std::vector<std::pair<std::string, TuneEntry>> out;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t q0 = line.find('"');
+        if (q0 == std::string::npos) continue;
+        const size_t q1 = line.find('"', q0 + 1);
+        if (q1 == std::string::npos) continue;
+        TuneEntry e;
+        if (std::sscanf(line.c_str() + q1 + 1,
+                        ": {\"threads_per_sentence\": %d, \"count_records\": %d, \"chunk_arcs\": %d, \"ms\": %f",
+                        &e.nt, &e.mode, &e.chunk, &e.ms) == 4)
+            out.emplace_back(line.substr(q0 + 1, q1 - q0 - 1), e);
+    }
+    return out;
+}
+
+int write_tune_cache(const char *path, const std::vector<std::pair<std::string, TuneEntry>> &entries)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream o(tmp, std::ios::trunc);
+        if (!o) return set_err(WFST_EINVAL, std::string("can not write the autotune cache ") + path);
+        o << "{\n";
+        for (size_t i = 0; i < entries.size(); ++i) {
+            const TuneEntry &e = entries[i].second;
+            char buf[160];
+            std::snprintf(buf, sizeof(buf),
+                          ": {\"threads_per_sentence\": %d, \"count_records\": %d, \"chunk_arcs\": %d, \"ms\": %.4f}",
+                          e.nt, e.mode, e.chunk, e.ms);
+            o << "\"" << entries[i].first << "\"" << buf << (i + 1 < entries.size() ? ",\n" : "\n");
+        }
+        o << "}\n";
+        if (!o) return set_err(WFST_EINVAL, std::string("can not write the autotune cache ") + path);
+    }
+    if (std::rename(tmp.c_str(), path) != 0)
+        return set_err(WFST_EINVAL, std::string("can not replace the autotune cache ") + path);
+    return WFST_OK;
+}
+
+// Cache key: device architecture, FST shape and the batch's shape (sentences,
+// tokens, mean arcs per token, log2 histogram of sentence lengths).
+int tune_key(const wfst_fst *f, int32_t B, int64_t N, const int32_t *offsets, const int32_t *tokens,
+             int32_t flags, hipStream_t s, std::string &key)
+{
+    std::vector<int32_t> off((size_t)B + 1), tok((size_t)std::max<int64_t>(N, 1));
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipMemcpy(off.data(), offsets, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (N > 0) HIP_OK(hipMemcpy(tok.data(), tokens, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int hist[12] = {0};
+    for (int32_t b = 0; b < B; ++b) {
+        const int32_t T = off[(size_t)b + 1] - off[(size_t)b];
+        int k = 0;
+        while (k < 11 && (1 << k) <= T) ++k;
+        hist[k] += 1;
+    }
+    double arcs = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        const int32_t a = tok[(size_t)i];
+        if (a >= 0 && a < f->M) arcs += f->label_arcs[(size_t)a];
+    }
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, f->device));
+    std::ostringstream k;
+    k << prop.gcnArchName << " Q=" << f->Q << " M=" << f->M << " A=" << f->A << " B=" << B << " N=" << N
+      << " Aw=" << (int64_t)std::llround(N > 0 ? arcs / (double)N : 0.0) << " len=";
+    for (int i = 0; i < 12; ++i) k << (i ? "," : "") << hist[i];
+    k << " chunks=" << ((flags & WFST_TUNE_CHUNK) ? "tuned" : std::to_string(f->chunk));
+    key = k.str();
+    for (char &c : key)
+        if (c == '"' || c == '\\') c = '_';
     return WFST_OK;
 }
 
@@ -1482,26 +1669,54 @@ int wfst_forward_backward(const wfst_fst *f, int32_t batch, int64_t num_tokens, 
 }
 
 int wfst_fst_autotune(wfst_fst *f, int32_t batch, int64_t num_tokens, const int32_t *offsets,
-                      const int32_t *tokens, int32_t *threads_out, float *times_ms, void *stream)
+                      const int32_t *tokens, const char *cache_path, int32_t flags, wfst_autotune_result *res,
+                      void *stream)
 {
     if (!f) return set_err(WFST_EINVAL, "fst is NULL");
     TRY(check_batch(f, batch, num_tokens, offsets, tokens));
     static const int32_t sizes[5] = {64, 128, 256, 512, 1024};
-    float ms[5] = {-1.0f, -1.0f, -1.0f, -1.0f, -1.0f};
+    static const int32_t modes[3] = {0, -1, -2};
     hipStream_t s = as_stream(stream);
-    const int32_t keep = f->nt;
+    wfst_autotune_result r;
+    std::memset(&r, 0, sizeof(r));
+    for (int c = 0; c < 4; ++c)
+        for (int k = 0; k < 5; ++k)
+            for (int m = 0; m < 3; ++m) r.ms[c][k][m] = -1.0f;
+    const int32_t keep_nt = f->nt, keep_mode = count_mode(f), keep_chunk = f->chunk;
+    r.threads_per_sentence = keep_nt;
+    r.count_records = keep_mode;
+    r.chunk_arcs = keep_chunk;
+    r.best_ms = -1.0f;
     if (batch == 0) {
-        if (threads_out) *threads_out = keep;
-        if (times_ms) std::copy(ms, ms + 5, times_ms);
+        if (res) *res = r;
         return WFST_OK;
+    }
+    std::string key;
+    std::vector<std::pair<std::string, TuneEntry>> cache;
+    if (cache_path && *cache_path) {
+        TRY(tune_key(f, batch, num_tokens, offsets, tokens, flags, s, key));
+        cache = read_tune_cache(cache_path);
+        for (auto &e : cache)
+            if (e.first == key) {  // known workload: apply without timing
+                TRY(rebuild_layouts(f, e.second.chunk, s));
+                f->nt = e.second.nt;
+                set_count_mode(f, e.second.mode);
+                r.threads_per_sentence = f->nt;
+                r.count_records = e.second.mode;
+                r.chunk_arcs = f->chunk;
+                r.best_ms = e.second.ms;
+                r.from_cache = 1;
+                if (res) *res = r;
+                return WFST_OK;
+            }
     }
     // scratch outputs of the timed passes
     const int64_t N = num_tokens;
     const size_t bytes = (size_t)batch * (2 * sizeof(float) + sizeof(int32_t)) + (size_t)N * sizeof(int32_t) +
                          (size_t)std::max<int64_t>(f->A, 1) * sizeof(float);
-    void *scratch = nullptr;
-    if (hipMalloc(&scratch, bytes) != hipSuccess) return set_err(WFST_ENOMEM, "autotune scratch");
-    float *score = static_cast<float *>(scratch);
+    void *scratch_out = nullptr;
+    if (hipMalloc(&scratch_out, bytes) != hipSuccess) return set_err(WFST_ENOMEM, "autotune scratch");
+    float *score = static_cast<float *>(scratch_out);
     float *log_z = score + batch;
     int32_t *status = reinterpret_cast<int32_t *>(log_z + batch);
     int32_t *arcs = status + batch;
@@ -1513,43 +1728,80 @@ int wfst_fst_autotune(wfst_fst *f, int32_t batch, int64_t num_tokens, const int3
         TRY(wfst_viterbi(f, batch, N, offsets, tokens, score, arcs, nullptr, status, s));
         wfst_tape *t = nullptr;
         TRY(wfst_forward(f, batch, N, offsets, tokens, log_z, status, &t, s));
-        const int r = wfst_backward(f, t, nullptr, grad, nullptr, s);
+        const int rb = wfst_backward(f, t, nullptr, grad, nullptr, s);
         wfst_tape_free(t);
-        return r;
+        return rb;
     };
-    int best = -1;
-    for (int k = 0; k < 5 && rc == WFST_OK; ++k) {
-        f->nt = sizes[k];
-        int r = pass();  // untimed: grows workspaces, loads code
-        if (r == WFST_EUNSUPPORTED) continue;  // this size does not fit the FST's LDS needs
-        if (r != WFST_OK) {
-            rc = r;
-            break;
+    std::vector<int32_t> chunks;
+    if (flags & WFST_TUNE_CHUNK) chunks = {4, 8, 16, 32};
+    else chunks = {keep_chunk};
+    int bc = -1, bk = -1, bm = -1;
+    for (size_t c = 0; c < chunks.size() && rc == WFST_OK; ++c) {
+        r.chunks[c] = chunks[c];
+        if ((rc = rebuild_layouts(f, chunks[c], s)) != WFST_OK) break;
+        for (int k = 0; k < 5 && rc == WFST_OK; ++k) {
+            for (int m = 0; m < 3 && rc == WFST_OK; ++m) {
+                f->nt = sizes[k];
+                // records and the grouped kernel need the on-chip backward sweep, the
+                // grouped kernel its own state in LDS too
+                if (modes[m] != -2 && backward_in_gmem(f)) continue;
+                if (modes[m] == -1 && lds_counts(f) > f->max_lds) continue;
+                set_count_mode(f, modes[m]);
+                int p = pass();  // untimed: grows workspaces, loads code
+                if (p == WFST_EUNSUPPORTED) continue;  // this size does not fit the FST's needs
+                if (p != WFST_OK) {
+                    rc = p;
+                    break;
+                }
+                if (hipEventRecord(e0, s) != hipSuccess) {
+                    rc = set_err(WFST_EHIP, "event");
+                    break;
+                }
+                if ((p = pass()) != WFST_OK) {
+                    rc = p;
+                    break;
+                }
+                float ms = 0.0f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = set_err(WFST_EHIP, "event timing");
+                    break;
+                }
+                r.ms[c][k][m] = ms;
+                r.tried += 1;
+                if (bc < 0 || ms < r.ms[bc][bk][bm]) {
+                    bc = (int)c;
+                    bk = k;
+                    bm = m;
+                }
+            }
         }
-        if (hipEventRecord(e0, s) != hipSuccess) {
-            rc = set_err(WFST_EHIP, "event");
-            break;
-        }
-        if ((r = pass()) != WFST_OK) {
-            rc = r;
-            break;
-        }
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms[k], e0, e1) != hipSuccess) {
-            rc = set_err(WFST_EHIP, "event timing");
-            break;
-        }
-        if (best < 0 || ms[k] < ms[best]) best = k;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
-    (void)hipFree(scratch);
-    if (rc == WFST_OK && best < 0) rc = set_err(WFST_EUNSUPPORTED, "no workgroup size fits this FST");
-    f->nt = rc == WFST_OK ? sizes[best] : keep;
+    (void)hipFree(scratch_out);
+    if (rc == WFST_OK && bc < 0) rc = set_err(WFST_EUNSUPPORTED, "no configuration fits this FST");
+    const int32_t chunk = rc == WFST_OK ? chunks[(size_t)bc] : keep_chunk;
+    const int rr = rebuild_layouts(f, chunk, s);
+    if (rc == WFST_OK) rc = rr;
+    f->nt = rc == WFST_OK ? sizes[bk] : keep_nt;
+    set_count_mode(f, rc == WFST_OK ? modes[bm] : keep_mode);
     if (rc != WFST_OK) return rc;
-    if (threads_out) *threads_out = f->nt;
-    if (times_ms) std::copy(ms, ms + 5, times_ms);
+    r.threads_per_sentence = f->nt;
+    r.count_records = modes[bm];
+    r.chunk_arcs = f->chunk;
+    r.best_ms = r.ms[bc][bk][bm];
+    if (!key.empty()) {
+        TuneEntry e;
+        e.nt = f->nt;
+        e.mode = modes[bm];
+        e.chunk = f->chunk;
+        e.ms = r.best_ms;
+        cache.emplace_back(key, e);
+        TRY(write_tune_cache(cache_path, cache));
+    }
+    if (res) *res = r;
     return WFST_OK;
 }
 
