@@ -411,10 +411,32 @@ def main():
         P4 = min(max(args.per_sentence, 1), b4.size)
         log(f"  per-sentence form on {P4} sentences")
         ps4 = per_sentence_rates(wf, d4, b4, off4, tok4, P4)
+        log("  graphs: the batched pass as one replay, and one graph per sentence")
+        n4 = int(b4.offsets[-1])
+        g4 = wf.Graph(d4, off4, tok4)
+        ms_g4, _ = time_steps(g4.replay, args.steps, args.warmup)
+        g4.close()
+        graphs1 = []
+        for b in range(P4):
+            o1 = torch.tensor([0, int(b4.offsets[b + 1] - b4.offsets[b])], dtype=torch.int32, device=dev)
+            graphs1.append(wf.Graph(d4, o1, tok4[int(b4.offsets[b]):int(b4.offsets[b + 1])]))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for g1 in graphs1:
+            g1.replay()
+        torch.cuda.synchronize()
+        tg1 = time.perf_counter() - t
+        for g1 in graphs1:
+            g1.close()
+        del graphs1
+        graph4 = {"batched_viterbi_plus_fwd_bwd_symbols_per_s": round(n4 / (ms_g4 * 1e-3), 1),
+                  "batched_ms_per_replay": round(ms_g4, 4),
+                  "per_sentence_graph_viterbi_plus_fwd_bwd_symbols_per_s": round(ps4["symbols"] / tg1, 1),
+                  "note": "graphs take fixed-point counts where the eager calls take per-visit records"}
         bigram = {"workload": f"bigram tagger WFST: 45 tags, 46 states, vocab 200000, {f4.num_arcs} arcs; "
                               f"{b4.size} sentences, {int(b4.offsets[-1])} symbols (lengths uniform 1..200)",
                   "autotune": tune4,
-                  "batched": rates4, "per_sentence": ps4,
+                  "batched": rates4, "per_sentence": ps4, "graphs": graph4,
                   "batched_over_per_sentence": {
                       "viterbi": round(rates4["viterbi_symbols_per_s"] / ps4["viterbi_symbols_per_s"], 1),
                       "fwd_bwd": round(rates4["fwd_bwd_symbols_per_s"] / ps4["fwd_bwd_symbols_per_s"], 1)},

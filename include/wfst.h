@@ -299,6 +299,64 @@ int wfst_fst_autotune(wfst_fst *fst, int32_t batch, int64_t num_tokens, const in
                       const int32_t *tokens, const char *cache_path, int32_t flags,
                       wfst_autotune_result *result, void *stream);
 
+/*
+ * HIP graphs of a whole batched pass sequence (the batching step of the
+ * method: section 5 launches one kernel per input symbol, and section 7.5
+ * finds launch overhead dominating small FSTs; here a pass is a few
+ * persistent launches, and a graph replays all of them, with the plan and
+ * count kernels around them, as one submission).
+ *
+ * wfst_graph_create captures, for one batch shape and one set of argument
+ * pointers (all DEVICE memory, bound into the graph):
+ *   1. when arc_score != NULL: wfst_fst_set_scores(fst, arc_score, NULL),
+ *   2. when best_score != NULL: wfst_viterbi into best_score / best_arcs /
+ *      best_olabels (nullable) / status,
+ *   3. when log_z != NULL: wfst_forward into log_z / status, then, when
+ *      grad_arc_score != NULL, wfst_backward with grad_log_z (nullable =
+ *      ones) into grad_arc_score and grad_final (nullable).
+ * A replay (wfst_graph_launch) computes the same as those calls on whatever
+ * the bound input buffers hold at that time (same batch and token counts),
+ * bit for bit, except that counts the eager call would take from per-visit
+ * records are taken in fixed point (equal to an eager call with
+ * count_records = -2 bit for bit, and to the records within the posterior
+ * accuracy).  The graph has its own
+ * workspace and tape buffers, so eager calls on the FST between replays are
+ * allowed (on the same stream).  Inside a graph nothing is read back to the
+ * host, so:
+ *   - buffers are sized by the bound num_tokens x (largest destination-
+ *     segment count of a label); bounds above 2 GiB give WFST_EUNSUPPORTED;
+ *   - the forward tape is kept whole (checkpointing needs device totals):
+ *     a bound above the tape budget, or checkpoint = 1, gives EUNSUPPORTED;
+ *   - counts that would take per-visit records take the fixed-point path.
+ * Creation runs the sequence once eagerly (its outputs are written), then
+ * captures it on `stream`, which must be a created stream (not the null
+ * stream); it synchronises the stream.  Layout rebuilds by the autotuner are
+ * refused while graphs of the FST exist.  Destroy graphs before the FST.
+ * A replay with arc_score counts as a score update for earlier tapes.
+ */
+typedef struct wfst_graph wfst_graph;
+
+typedef struct wfst_graph_args {
+    int32_t batch;
+    int64_t num_tokens;
+    const int32_t *offsets;        /* [batch+1] */
+    const int32_t *tokens;         /* [num_tokens] */
+    const float *arc_score;        /* [num_arcs] or NULL: scores set at the start of every replay */
+    float *best_score;             /* [batch] or NULL: no Viterbi */
+    int32_t *best_arcs;            /* [num_tokens] (with best_score) */
+    int32_t *best_olabels;         /* [num_tokens] or NULL */
+    float *log_z;                  /* [batch] or NULL: no forward-backward */
+    const float *grad_log_z;       /* [batch] or NULL (ones) */
+    float *grad_arc_score;         /* [num_arcs] or NULL: forward only */
+    float *grad_final;             /* [num_states] or NULL */
+    int32_t *status;               /* [batch], required */
+} wfst_graph_args;
+
+int wfst_graph_create(wfst_fst *fst, const wfst_graph_args *args, void *stream, wfst_graph **out);
+int wfst_graph_launch(wfst_graph *graph, void *stream);
+/* Synchronises the graph's device, then frees it.  NULL-safe. */
+void wfst_graph_destroy(wfst_graph *graph);
+
 /* Message for the last nonzero return on this thread ("" if none). */
 const char *wfst_last_error(void);
 

@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "WfstError", "Fst", "Tape", "viterbi", "viterbi_noalloc", "forward", "backward", "forward_backward",
+    "WfstError", "Fst", "Tape", "Graph", "viterbi", "viterbi_noalloc", "forward", "backward", "forward_backward",
     "LogPartition", "log_partition", "load_library", "layout_host", "library_path",
     "STATUS_OK", "STATUS_NO_PATH", "STATUS_BAD_TOKEN", "STATUS_BAD_INPUT",
 ]
@@ -58,6 +58,14 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64)]
 
 
+class _GraphArgs(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("num_tokens", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("tokens", ctypes.c_void_p), ("arc_score", ctypes.c_void_p), ("best_score", ctypes.c_void_p),
+                ("best_arcs", ctypes.c_void_p), ("best_olabels", ctypes.c_void_p), ("log_z", ctypes.c_void_p),
+                ("grad_log_z", ctypes.c_void_p), ("grad_arc_score", ctypes.c_void_p),
+                ("grad_final", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
 class _TuneResult(ctypes.Structure):
     _fields_ = [("threads_per_sentence", ctypes.c_int32), ("count_records", ctypes.c_int32),
                 ("chunk_arcs", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("tried", ctypes.c_int32),
@@ -74,7 +82,8 @@ EXPORTS = (
     "wfst_fst_profile", "wfst_fst_profile_read", "wfst_fst_label_stats",
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
-    "wfst_fst_score_version", "wfst_viterbi_noalloc",
+    "wfst_fst_score_version", "wfst_viterbi_noalloc", "wfst_graph_create", "wfst_graph_launch",
+    "wfst_graph_destroy",
 )
 
 
@@ -110,11 +119,15 @@ def load_library(path: str | None = None):
     lib.wfst_layout_host.argtypes = [i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
     lib.wfst_fst_autotune.argtypes = [P, i32, i64, P, P, ctypes.c_char_p, i32, ctypes.POINTER(_TuneResult), P]
     lib.wfst_fst_score_version.argtypes = [P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.wfst_graph_create.argtypes = [P, ctypes.POINTER(_GraphArgs), P, ctypes.POINTER(P)]
+    lib.wfst_graph_launch.argtypes = [P, P]
+    lib.wfst_graph_destroy.argtypes = [P]
+    lib.wfst_graph_destroy.restype = None
     for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health",
                  "wfst_fst_score_version", "wfst_fst_profile", "wfst_fst_profile_read",
                  "wfst_fst_label_stats", "wfst_viterbi", "wfst_viterbi_noalloc",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
-                 "wfst_fst_autotune"):
+                 "wfst_fst_autotune", "wfst_graph_create", "wfst_graph_launch"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -388,6 +401,60 @@ def forward_backward(fst: Fst, offsets, tokens, final_posteriors=False):
     _check(_lib.wfst_forward_backward(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(log_z),
                                       _dptr(post), _dptr(fpost), _dptr(status), _stream()))
     return (log_z, post, fpost, status) if final_posteriors else (log_z, post, status)
+
+
+class Graph:
+    """A captured batched pass sequence (wfst_graph_create): optional score
+    update, Viterbi, forward and backward with expected counts, for one batch
+    shape.  The offsets/tokens (and arc_score / grad_log_z) tensors are bound
+    into the graph; replay() reruns the sequence on their current contents
+    and writes the output tensors held by this object."""
+
+    def __init__(self, fst, offsets, tokens, viterbi=True, forward_backward=True, backward=True,
+                 arc_score=None, grad_log_z=None, final=False, olabels=False):
+        import torch
+        off, tok, B, N = _batch(offsets, tokens)
+        dev = off.device
+        self.fst, self.offsets, self.tokens = fst, off, tok
+        self.arc_score = None if arc_score is None else arc_score.detach().contiguous()
+        self.grad_log_z = None if grad_log_z is None else grad_log_z.to(torch.float32).contiguous()
+        self.status = torch.empty(B, dtype=torch.int32, device=dev)
+        f32, i32 = torch.float32, torch.int32
+        self.best_score = torch.empty(B, dtype=f32, device=dev) if viterbi else None
+        self.best_arcs = torch.empty(N, dtype=i32, device=dev) if viterbi else None
+        self.best_olabels = torch.empty(N, dtype=i32, device=dev) if viterbi and olabels else None
+        self.log_z = torch.empty(B, dtype=f32, device=dev) if forward_backward else None
+        self.grad = torch.empty(fst.num_arcs, dtype=f32, device=dev) if forward_backward and backward else None
+        self.grad_final = (torch.empty(fst.num_states, dtype=f32, device=dev)
+                           if forward_backward and backward and final else None)
+        args = _GraphArgs(B, N, off.data_ptr(), tok.data_ptr(), *(
+            (t.data_ptr() if t is not None else None) for t in (
+                self.arc_score, self.best_score, self.best_arcs, self.best_olabels, self.log_z, self.grad_log_z,
+                self.grad, self.grad_final, self.status)))
+        side = torch.cuda.Stream(device=dev)  # capture needs a created stream
+        side.wait_stream(torch.cuda.current_stream(dev))
+        h = ctypes.c_void_p()
+        with torch.cuda.stream(side):
+            _check(_lib.wfst_graph_create(fst.handle, ctypes.byref(args), _stream(dev), ctypes.byref(h)))
+        torch.cuda.current_stream(dev).wait_stream(side)
+        self._h = h
+
+    def replay(self):
+        """Queue one replay on the current stream."""
+        if self._h is None:
+            raise WfstError(WFST_EINVAL, "graph destroyed")
+        _check(_lib.wfst_graph_launch(self._h, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.wfst_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _make_log_partition():

@@ -119,6 +119,8 @@ struct wfst_fst {
     int32_t ckpt_mode = 0;                        // wfst_options.checkpoint
     int32_t state_mem = 0;                        // wfst_options.state_memory
     bool fx_counts = false;                       // counts by fixed-point accumulation (count_records = -2)
+    bool graph_mode = false;                      // capturing a graph: no host read-back, no records
+    int32_t live_graphs = 0;                      // graphs made on this FST and not destroyed
     uint64_t score_version = 0;                   // bumped by every score update
     int64_t tape_budget = (int64_t)8 << 30;       // bytes of alpha + beta tape before auto checkpointing
     int64_t A = 0;
@@ -165,6 +167,15 @@ struct wfst_tape {
     int64_t *ck_off = nullptr;    // [N] offset of a kept token's alpha~, -1 otherwise
     int64_t *blk_base = nullptr;  // [B] start of each sentence in a block buffer
     int64_t blk_total = 0;        // floats of one block buffer
+};
+
+struct wfst_graph {
+    wfst_fst *fst = nullptr;
+    wfst_graph_args args{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Buf ws[W_NUM];                   // the graph's own workspace (eager calls never resize it)
+    std::vector<TapeBufs *> pool;    // ... and tape buffers
 };
 
 namespace {
@@ -409,6 +420,10 @@ int make_plan(const wfst_fst *f, hipStream_t s, int32_t B, int64_t N, const int3
     const int64_t bound = N * (int64_t)std::max(f->fwd.max_segs, 1);
     if (bound <= bound_cap_elems) {
         p.total = bound;
+    } else if (f->graph_mode) {
+        return set_err(WFST_EUNSUPPORTED, "a graph sizes its buffers by the bound tokens x largest label (" +
+                                              std::to_string(bound) + " entries), which exceeds " +
+                                              std::to_string(bound_cap_elems) + "; use a smaller batch");
     } else {
         int64_t t = 0;
         HIP_OK(hipMemcpyAsync(&t, dev_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -446,6 +461,10 @@ int plan_checkpoints(wfst_fst *f, hipStream_t s, wfst_tape *t, int64_t *tiles, i
     if (f->ckpt_mode == 2 || N == 0) return WFST_OK;
     const int64_t bytes_bound = 2 * (int64_t)sizeof(float) * p.total;
     if (f->ckpt_mode != 1 && bytes_bound <= f->tape_budget) return WFST_OK;
+    if (f->graph_mode)
+        return set_err(WFST_EUNSUPPORTED, "a graph keeps the whole forward tape (checkpointing plans from "
+                                          "device totals); its bound exceeds the tape budget or checkpointing "
+                                          "is forced");
     // exact tape size and longest sentence
     int32_t *dev_tmax = reinterpret_cast<int32_t *>(dev_total + 1);
     hipLaunchKernelGGL(batch_max_len, dim3(1), dim3(1024), 0, s, t->offsets, B, dev_tmax);
@@ -810,6 +829,8 @@ int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
 {
     if (chunk == f->chunk) return WFST_OK;
     if (chunk < 1 || chunk > 64) return set_err(WFST_EINVAL, "chunk_arcs must be in [1, 64]");
+    if (f->live_graphs > 0)
+        return set_err(WFST_EINVAL, "the FST has graphs that point at its layouts; destroy them before a rebuild");
     const DevLayout &d = f->fwd;
     HIP_OK(hipStreamSynchronize(s));
     std::vector<int32_t> other((size_t)d.n_elem), earc((size_t)d.n_elem), seg_key((size_t)d.n_seg);
@@ -1439,7 +1460,9 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     const int64_t N = tape->N;
     // expected counts by fixed-point accumulation in the backward sweep: asked
     // for, or forced by a backward state too large for LDS
-    const bool fx = f->A > 0 && B > 0 && N > 0 && (f->fx_counts || backward_in_gmem(f));
+    // (a graph takes fixed-point counts where the records would need a read-back)
+    const bool fx = f->A > 0 && B > 0 && N > 0 &&
+                    (f->fx_counts || backward_in_gmem(f) || (f->graph_mode && !f->rec_off));
     if (f->A > 0 && !fx) {
         ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
         hipLaunchKernelGGL(fill_f32, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s, grad_arc_score, f->A, 0.0f);
@@ -1803,6 +1826,119 @@ int wfst_fst_autotune(wfst_fst *f, int32_t batch, int64_t num_tokens, const int3
     }
     if (res) *res = r;
     return WFST_OK;
+}
+
+// One pass sequence of a graph (scores, Viterbi, forward, backward), as the
+// eager entry points queue it.
+static int graph_sequence(wfst_fst *f, const wfst_graph_args &a, void *stream)
+{
+    if (a.arc_score) TRY(wfst_fst_set_scores(f, a.arc_score, nullptr, stream));
+    if (a.best_score)
+        TRY(wfst_viterbi(f, a.batch, a.num_tokens, a.offsets, a.tokens, a.best_score, a.best_arcs, a.best_olabels,
+                         a.status, stream));
+    if (a.log_z) {
+        wfst_tape *t = nullptr;
+        TRY(wfst_forward(f, a.batch, a.num_tokens, a.offsets, a.tokens, a.log_z, a.status, &t, stream));
+        const int r = a.grad_arc_score ? wfst_backward(f, t, a.grad_log_z, a.grad_arc_score, a.grad_final, stream)
+                                       : WFST_OK;
+        wfst_tape_free(t);
+        TRY(r);
+    }
+    return WFST_OK;
+}
+
+static void graph_free(wfst_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (Buf &b : g->ws) free_buf(b);
+    for (TapeBufs *t : g->pool) {
+        for (Buf *b : {&t->order, &t->tok_off, &t->alpha, &t->a_max, &t->a_log, &t->log_z, &t->tiles, &t->total,
+                       &t->ck_size, &t->ck_off, &t->blk_size, &t->blk_base})
+            free_buf(*b);
+        delete t;
+    }
+    delete g;
+}
+
+int wfst_graph_create(wfst_fst *f, const wfst_graph_args *args, void *stream, wfst_graph **out)
+{
+    if (!out) return set_err(WFST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!f || !args) return set_err(WFST_EINVAL, "NULL fst or args");
+    const wfst_graph_args &a = *args;
+    TRY(check_batch(f, a.batch, a.num_tokens, a.offsets, a.tokens));
+    if (!a.best_score && !a.log_z) return set_err(WFST_EINVAL, "a graph needs Viterbi or forward outputs");
+    if (!a.status) return set_err(WFST_EINVAL, "status is NULL");
+    if (a.grad_final && !a.grad_arc_score) return set_err(WFST_EINVAL, "grad_final needs grad_arc_score");
+    hipStream_t s = as_stream(stream);
+    if (s == nullptr) return set_err(WFST_EINVAL, "graphs are captured on a created stream, not the null stream");
+    wfst_graph *g = new wfst_graph();
+    g->fst = f;
+    g->args = a;
+    const bool prof = f->prof;
+    auto enter = [&]() {
+        for (int i = 0; i < W_NUM; ++i) std::swap(f->ws[i], g->ws[i]);
+        std::swap(f->tape_pool, g->pool);
+        f->prof = false;
+        f->graph_mode = true;
+    };
+    auto leave = [&]() {
+        for (int i = 0; i < W_NUM; ++i) std::swap(f->ws[i], g->ws[i]);
+        std::swap(f->tape_pool, g->pool);
+        f->prof = prof;
+        f->graph_mode = false;
+    };
+    enter();
+    // eager run: sizes the graph's buffers (nothing grows during capture) and checks the arguments
+    int rc = graph_sequence(f, a, stream);
+    if (rc == WFST_OK && hipStreamSynchronize(s) != hipSuccess) rc = set_err(WFST_EHIP, "eager pass of the graph");
+    if (rc == WFST_OK) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            rc = set_err(WFST_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        } else {
+            rc = graph_sequence(f, a, stream);
+            e = hipStreamEndCapture(s, &g->graph);
+            if (rc == WFST_OK && e != hipSuccess)
+                rc = set_err(WFST_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        }
+    }
+    leave();
+    if (rc == WFST_OK) {
+        const hipError_t e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = set_err(WFST_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (rc != WFST_OK) {
+        (void)hipStreamSynchronize(s);
+        graph_free(g);
+        return rc;
+    }
+    f->live_graphs += 1;
+    *out = g;
+    return WFST_OK;
+}
+
+int wfst_graph_launch(wfst_graph *g, void *stream)
+{
+    if (!g || !g->exec) return set_err(WFST_EINVAL, "graph is NULL");
+    HIP_OK(hipGraphLaunch(g->exec, as_stream(stream)));
+    if (g->args.arc_score) g->fst->score_version += 1;  // the replay replaced the scores
+    return WFST_OK;
+}
+
+void wfst_graph_destroy(wfst_graph *g)
+{
+    if (!g) return;
+    int cur = 0;
+    const int dev = g->fst->device;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != dev;
+    if (other) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    g->fst->live_graphs -= 1;
+    graph_free(g);
+    if (other) (void)hipSetDevice(cur);
 }
 
 }  // extern "C"
