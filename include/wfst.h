@@ -300,6 +300,27 @@ int wfst_fst_autotune(wfst_fst *fst, int32_t batch, int64_t num_tokens, const in
                       wfst_autotune_result *result, void *stream);
 
 /*
+ * EM M-step (paper, section 4: the expected counts of Algorithm 2 serve
+ * expectation-maximisation of the transducer's weights).  The FST is read as
+ * a locally normalised model p(arc | source state) with fixed final weights:
+ *   new_score[k] = log(counts[k] + smoothing)
+ *                  - log(sum over arcs j leaving src_k of (counts[j] + smoothing)),
+ * and the arcs of a state whose total is 0 keep cur_score.  With smoothing 0
+ * and counts from wfst_backward (grad_log_z = ones) under cur_score, this is
+ * one EM iteration, which cannot lower sum_b log Z_b.
+ *   counts, cur_score: DEVICE float[num_arcs] (arc-id order).
+ *   new_score: DEVICE float[num_arcs], may be cur_score; apply it with
+ *     wfst_fst_set_scores.
+ *   smoothing: finite, >= 0 (else WFST_EINVAL).
+ * Per-state totals are summed in FP64 in a fixed order: results are bitwise
+ * reproducible.  The first call on an FST builds an index of its arcs by
+ * source state (read back from the device layout; synchronises the stream;
+ * 8 bytes per arc of device memory).
+ */
+int wfst_em_update(wfst_fst *fst, const float *counts, float smoothing, const float *cur_score,
+                   float *new_score, void *stream);
+
+/*
  * HIP graphs of a whole batched pass sequence (the batching step of the
  * method: section 5 launches one kernel per input symbol, and section 7.5
  * finds launch overhead dominating small FSTs; here a pass is a few
@@ -356,6 +377,35 @@ int wfst_graph_create(wfst_fst *fst, const wfst_graph_args *args, void *stream, 
 int wfst_graph_launch(wfst_graph *graph, void *stream);
 /* Synchronises the graph's device, then frees it.  NULL-safe. */
 void wfst_graph_destroy(wfst_graph *graph);
+
+/*
+ * Reader for the AT&T / OpenFST text format (paper, section 7.2: the FSTs are
+ * read from OpenFST's text form; section 5.1: output symbols of the best path
+ * are looked up in O).  Host only, no GPU.
+ *   fst_text[fst_len]: lines "src dst ilabel olabel [weight]" (an arc) or
+ *     "state [weight]" (a final state), blank/tab separated.  The source of
+ *     the first line is the start state.  Weights are costs (-log p): the
+ *     score is -weight, a missing weight is 0; a final weight "inf" /
+ *     "Infinity" marks a non-final state.  Arc weights must be finite.
+ *   isyms_text / osyms_text (nullable, with lengths): symbol tables, lines
+ *     "symbol id"; labels that are not in the table must be non-negative
+ *     integers.
+ *   epsilon_zero != 0: label id 0 is epsilon, and an epsilon input label is
+ *     refused with WFST_EUNSUPPORTED (the method has no epsilon transitions,
+ *     section 3).
+ * First call with all arrays NULL: counts[4] (HOST) receives {num_states =
+ * largest state id + 1, num_ilabels = largest input id (of the arcs or the
+ * input table) + 1, num_arcs, start}.  Second call: HOST arrays src, dst,
+ * ilabel, olabel (nullable), arc_score [num_arcs] and final_score
+ * [num_states] (-inf for non-final states), arcs in file order (arc id =
+ * line order), ready for wfst_fst_create.  Errors name the line; the message
+ * comes from wfst_att_last_error().
+ */
+int wfst_att_parse(const char *fst_text, int64_t fst_len, const char *isyms_text, int64_t isyms_len,
+                   const char *osyms_text, int64_t osyms_len, int32_t epsilon_zero, int64_t *counts,
+                   int32_t *src, int32_t *dst, int32_t *ilabel, int32_t *olabel, float *arc_score,
+                   float *final_score);
+const char *wfst_att_last_error(void);
 
 /* Message for the last nonzero return on this thread ("" if none). */
 const char *wfst_last_error(void);

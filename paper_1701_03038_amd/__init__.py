@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "WfstError", "Fst", "Tape", "Graph", "viterbi", "viterbi_noalloc", "forward", "backward", "forward_backward",
-    "LogPartition", "log_partition", "load_library", "layout_host", "library_path",
+    "LogPartition", "log_partition", "em_update", "em_step", "read_att", "AttFst", "load_library", "layout_host", "library_path",
     "STATUS_OK", "STATUS_NO_PATH", "STATUS_BAD_TOKEN", "STATUS_BAD_INPUT",
 ]
 
@@ -83,7 +83,7 @@ EXPORTS = (
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
     "wfst_fst_score_version", "wfst_viterbi_noalloc", "wfst_graph_create", "wfst_graph_launch",
-    "wfst_graph_destroy",
+    "wfst_graph_destroy", "wfst_em_update", "wfst_att_parse", "wfst_att_last_error",
 )
 
 
@@ -123,11 +123,17 @@ def load_library(path: str | None = None):
     lib.wfst_graph_launch.argtypes = [P, P]
     lib.wfst_graph_destroy.argtypes = [P]
     lib.wfst_graph_destroy.restype = None
+    lib.wfst_em_update.argtypes = [P, P, ctypes.c_float, P, P, P]
+    lib.wfst_att_parse.argtypes = [ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.c_char_p, i64, i32, P,
+                                   P, P, P, P, P, P]
+    lib.wfst_att_parse.restype = ctypes.c_int
+    lib.wfst_att_last_error.argtypes = []
+    lib.wfst_att_last_error.restype = ctypes.c_char_p
     for name in ("wfst_fst_create", "wfst_fst_set_scores", "wfst_fst_get_info", "wfst_fst_health",
                  "wfst_fst_score_version", "wfst_fst_profile", "wfst_fst_profile_read",
                  "wfst_fst_label_stats", "wfst_viterbi", "wfst_viterbi_noalloc",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
-                 "wfst_fst_autotune", "wfst_graph_create", "wfst_graph_launch"):
+                 "wfst_fst_autotune", "wfst_graph_create", "wfst_graph_launch", "wfst_em_update"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -401,6 +407,96 @@ def forward_backward(fst: Fst, offsets, tokens, final_posteriors=False):
     _check(_lib.wfst_forward_backward(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(log_z),
                                       _dptr(post), _dptr(fpost), _dptr(status), _stream()))
     return (log_z, post, fpost, status) if final_posteriors else (log_z, post, status)
+
+
+class AttFst:
+    """Arrays of an FST read from AT&T / OpenFST text (wfst_att_parse), with
+    its symbol tables (id -> symbol) when given; Fst.from_synth accepts it."""
+
+    def __init__(self, num_states, num_ilabels, start, src, dst, ilabel, olabel, arc_score, final_score,
+                 isyms=None, osyms=None):
+        self.num_states, self.num_ilabels, self.start = num_states, num_ilabels, start
+        self.src, self.dst, self.ilabel, self.olabel = src, dst, ilabel, olabel
+        self.arc_score, self.final_score = arc_score, final_score
+        self.isyms, self.osyms = isyms, osyms
+
+    @property
+    def num_arcs(self):
+        return int(self.src.shape[0])
+
+    def encode(self, words):
+        """Token ids of a sequence of input symbols."""
+        inv = {s: i for i, s in (self.isyms or {}).items()}
+        return np.array([inv[w] for w in words], np.int32)
+
+    def output_strings(self, best_olabels, offsets):
+        """Output symbols of each sentence's best path (best_olabels from
+        viterbi(..., olabels=True); -1 marks a sentence without a path)."""
+        ol = np.asarray(best_olabels)
+        off = np.asarray(offsets)
+        out = []
+        for b in range(off.shape[0] - 1):
+            ids = ol[int(off[b]):int(off[b + 1])]
+            if ids.size and ids[0] < 0:
+                out.append(None)
+            else:
+                out.append([self.osyms[int(i)] if self.osyms else str(int(i)) for i in ids])
+        return out
+
+
+def _symbols(text):
+    table = {}
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) == 2:
+            table[int(f[1])] = f[0]
+    return table
+
+
+def read_att(fst_text: str, isyms: str | None = None, osyms: str | None = None, epsilon_zero: bool = False):
+    """Parse an FST in AT&T / OpenFST text form (strings, not paths) with
+    optional symbol tables; returns an AttFst."""
+    lib = load_library()
+    t = fst_text.encode()
+    it = isyms.encode() if isyms is not None else None
+    ot = osyms.encode() if osyms is not None else None
+    args = (t, len(t), it, len(it) if it else 0, ot, len(ot) if ot else 0, int(epsilon_zero))
+    counts = np.zeros(4, np.int64)
+
+    def check(rc):
+        if rc != 0:
+            raise WfstError(rc, lib.wfst_att_last_error().decode(errors="replace"))
+    check(lib.wfst_att_parse(*args, _np_ptr(counts), None, None, None, None, None, None))
+    Q, M, A, start = (int(x) for x in counts)
+    arr = [np.empty(A, np.int32) for _ in range(4)]
+    sc, fin = np.empty(A, np.float32), np.empty(Q, np.float32)
+    check(lib.wfst_att_parse(*args, _np_ptr(counts), *(_np_ptr(a) for a in arr), _np_ptr(sc), _np_ptr(fin)))
+    return AttFst(Q, M, start, *arr, sc, fin, _symbols(isyms) if isyms else None,
+                  _symbols(osyms) if osyms else None)
+
+
+def em_update(fst: Fst, counts, cur_score, smoothing: float = 0.0, out=None):
+    """EM M-step: new log scores from expected counts (device float32 tensors
+    in arc-id order), normalised per source state (wfst_em_update)."""
+    import torch
+    for t in (counts, cur_score):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise WfstError(WFST_EINVAL, "counts and scores must be contiguous float32 device tensors")
+    out = torch.empty_like(cur_score) if out is None else out
+    _check(_lib.wfst_em_update(fst.handle, _dptr(counts), float(smoothing), _dptr(cur_score), _dptr(out),
+                               _stream()))
+    return out
+
+
+def em_step(fst: Fst, arc_score, offsets, tokens, smoothing: float = 0.0):
+    """One EM iteration on a batch: set the scores, forward-backward (expected
+    counts), M-step.  Returns (new scores f32[A], sum of log Z over the
+    sentences with a path under the given scores)."""
+    import torch
+    fst.set_scores(arc_score)
+    log_z, counts, status = forward_backward(fst, offsets, tokens)
+    ll = torch.where(status == STATUS_OK, log_z.double(), torch.zeros_like(log_z, dtype=torch.float64)).sum()
+    return em_update(fst, counts, arc_score, smoothing), ll
 
 
 class Graph:

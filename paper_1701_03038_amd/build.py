@@ -37,12 +37,15 @@ def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     os.makedirs(BUILD, exist_ok=True)
     lay_o = os.path.join(BUILD, "layout.o")
+    att_o = os.path.join(BUILD, "att.o")
     api_o = os.path.join(BUILD, "wfst_api.o")
     _run(["g++", "-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", "-I", INCLUDE,
           "-c", os.path.join(CSRC, "layout.cpp"), "-o", lay_o], verbose)
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I", INCLUDE,
+          "-c", os.path.join(CSRC, "att.cpp"), "-o", att_o], verbose)
     _run([hipcc, *HIP_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, "wfst_api.hip"), "-o", api_o], verbose)
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, api_o, lay_o, "-pthread"], verbose)
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, api_o, lay_o, att_o, "-pthread"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

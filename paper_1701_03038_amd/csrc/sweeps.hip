@@ -1978,6 +1978,37 @@ __global__ void fx_to_grad(const unsigned long long *__restrict__ acc, int64_t n
         grad[i] = (float)((double)(long long)acc[i] * inv);
 }
 
+// EM M-step, per-state totals: one wavefront per source state; lane l sums
+// the state's arcs l, l + 64, ... in order in FP64, then a fixed butterfly
+// combines the lanes, so the total has the same bits on every call.
+__global__ void em_source_sums(const int32_t *__restrict__ order, const int64_t *__restrict__ start, int32_t Q,
+                               const float *__restrict__ counts, float smoothing, double *__restrict__ sums)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = wave; q < Q; q += waves) {
+        double acc = 0.0;
+        for (int64_t i = start[q] + lane; i < start[q + 1]; i += 64) acc += (double)counts[order[i]] + (double)smoothing;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) sums[q] = acc;
+    }
+}
+
+// EM M-step, new scores: log(c_k + s) - log(total of the source state); a
+// state with zero total keeps its scores.  new_score may alias cur_score.
+__global__ void em_normalize(const int32_t *__restrict__ src, int64_t A, const float *__restrict__ counts,
+                             float smoothing, const double *__restrict__ sums, const float *cur_score,
+                             float *new_score)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < A; k += (int64_t)gridDim.x * blockDim.x) {
+        const double tot = sums[src[k]];
+        const double c = (double)counts[k] + (double)smoothing;
+        new_score[k] = tot > 0.0 ? (float)(log(c) - log(tot)) : cur_score[k];
+    }
+}
+
 __global__ void final_max_kernel(const float *__restrict__ fin, int32_t Q, float *__restrict__ out)
 {
     __shared__ float red[1024];

@@ -95,7 +95,7 @@ enum WsSlot {
     W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
-    W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_NUM
+    W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
@@ -121,6 +121,9 @@ struct wfst_fst {
     bool fx_counts = false;                       // counts by fixed-point accumulation (count_records = -2)
     bool graph_mode = false;                      // capturing a graph: no host read-back, no records
     int32_t live_graphs = 0;                      // graphs made on this FST and not destroyed
+    int32_t *em_order = nullptr;                  // EM: arc ids grouped by source state
+    int64_t *em_start = nullptr;                  // ... group starts [Q+1]
+    int32_t *em_src = nullptr;                    // ... source state of each arc
     uint64_t score_version = 0;                   // bumped by every score update
     int64_t tape_budget = (int64_t)8 << 30;       // bytes of alpha + beta tape before auto checkpointing
     int64_t A = 0;
@@ -822,15 +825,13 @@ void set_count_mode(wfst_fst *f, int32_t mode)
 
 int32_t count_mode(const wfst_fst *f) { return f->fx_counts ? -2 : (f->rec_off ? -1 : 0); }
 
-// Rebuild both layouts with another chunk length.  The arcs (label, source,
-// destination, id) and their current scores are read back from the forward
-// layout, so the FST keeps no host copy of its arcs.  Synchronises the stream.
-int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
+// The FST's arcs in id order (label, source, destination, current score),
+// read back from the forward layout: its slot (row r, lane l) of slice s
+// holds chunk s*64 + l of its label, whose segment's key is the destination.
+// Synchronises the stream.
+int read_arcs(wfst_fst *f, hipStream_t s, std::vector<int32_t> &src, std::vector<int32_t> &dst,
+              std::vector<int32_t> &ilabel, std::vector<float> &sc)
 {
-    if (chunk == f->chunk) return WFST_OK;
-    if (chunk < 1 || chunk > 64) return set_err(WFST_EINVAL, "chunk_arcs must be in [1, 64]");
-    if (f->live_graphs > 0)
-        return set_err(WFST_EINVAL, "the FST has graphs that point at its layouts; destroy them before a rebuild");
     const DevLayout &d = f->fwd;
     HIP_OK(hipStreamSynchronize(s));
     std::vector<int32_t> other((size_t)d.n_elem), earc((size_t)d.n_elem), seg_key((size_t)d.n_seg);
@@ -845,10 +846,10 @@ int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
     HIP_OK(hipMemcpy(slice.data(), d.slice, slice.size() * sizeof(SliceInfo), hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(seg_chunk.data(), d.seg_chunk, seg_chunk.size() * sizeof(SegChunk), hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(label.data(), d.label, label.size() * sizeof(LabelInfo), hipMemcpyDeviceToHost));
-    // arcs in id order: the forward layout's slot (row r, lane l) of slice s holds
-    // chunk s*64 + l of its label, whose segment's key is the destination
-    std::vector<int32_t> src((size_t)f->A, 0), dst((size_t)f->A, 0), ilabel((size_t)f->A, 0);
-    std::vector<float> sc((size_t)f->A, 0.0f);
+    src.assign((size_t)f->A, 0);
+    dst.assign((size_t)f->A, 0);
+    ilabel.assign((size_t)f->A, 0);
+    sc.assign((size_t)f->A, 0.0f);
     std::vector<int32_t> chunk_seg;
     for (int32_t a = 0; a < f->M; ++a) {
         const LabelInfo &li = label[(size_t)a];
@@ -875,9 +876,21 @@ int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
             }
         }
     }
-    std::vector<int32_t>().swap(other);
-    std::vector<int32_t>().swap(earc);
-    std::vector<float>().swap(score);
+    return WFST_OK;
+}
+
+// Rebuild both layouts with another chunk length from the arcs read back
+// from the forward layout (with their current scores), so the FST keeps no
+// host copy of its arcs.  Synchronises the stream.
+int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
+{
+    if (chunk == f->chunk) return WFST_OK;
+    if (chunk < 1 || chunk > 64) return set_err(WFST_EINVAL, "chunk_arcs must be in [1, 64]");
+    if (f->live_graphs > 0)
+        return set_err(WFST_EINVAL, "the FST has graphs that point at its layouts; destroy them before a rebuild");
+    std::vector<int32_t> src, dst, ilabel;
+    std::vector<float> sc;
+    TRY(read_arcs(f, s, src, dst, ilabel, sc));
     std::string err;
     HostLayout hf, hr;
     int rc = build_layout(f->Q, f->M, f->A, src.data(), dst.data(), ilabel.data(), sc.data(), 0, chunk, hf, err);
@@ -891,6 +904,28 @@ int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
     HIP_OK(hipStreamSynchronize(s));
     f->chunk = chunk;
     f->score_version += 1;  // tapes made on the old layouts are not used again
+    return WFST_OK;
+}
+
+// By-source index of the arcs for the EM M-step (built once per FST): arc
+// ids grouped by source state (increasing id inside a state), the group
+// starts, and each arc's source.
+int ensure_source_index(wfst_fst *f, hipStream_t s)
+{
+    if (f->em_src) return WFST_OK;
+    std::vector<int32_t> src, dst, ilabel;
+    std::vector<float> sc;
+    TRY(read_arcs(f, s, src, dst, ilabel, sc));
+    std::vector<int64_t> start((size_t)f->Q + 1, 0);
+    for (int64_t k = 0; k < f->A; ++k) start[(size_t)src[(size_t)k] + 1] += 1;
+    for (int32_t q = 0; q < f->Q; ++q) start[(size_t)q + 1] += start[(size_t)q];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    std::vector<int32_t> order((size_t)std::max<int64_t>(f->A, 1));
+    for (int64_t k = 0; k < f->A; ++k) order[(size_t)fill[(size_t)src[(size_t)k]]++] = (int32_t)k;
+    TRY(dev_upload(f, &f->em_order, order.data(), f->A, s));
+    TRY(dev_upload(f, &f->em_start, start.data(), (int64_t)start.size(), s));
+    TRY(dev_upload(f, &f->em_src, src.data(), f->A, s));
+    HIP_OK(hipStreamSynchronize(s));
     return WFST_OK;
 }
 
@@ -1825,6 +1860,25 @@ int wfst_fst_autotune(wfst_fst *f, int32_t batch, int64_t num_tokens, const int3
         TRY(write_tune_cache(cache_path, cache));
     }
     if (res) *res = r;
+    return WFST_OK;
+}
+
+int wfst_em_update(wfst_fst *f, const float *counts, float smoothing, const float *cur_score, float *new_score,
+                   void *stream)
+{
+    if (!f) return set_err(WFST_EINVAL, "fst is NULL");
+    if (f->A > 0 && (!counts || !cur_score || !new_score)) return set_err(WFST_EINVAL, "NULL argument");
+    if (!(smoothing >= 0.0f) || std::isinf(smoothing)) return set_err(WFST_EINVAL, "smoothing must be finite and >= 0");
+    if (f->A == 0) return WFST_OK;
+    hipStream_t s = as_stream(stream);
+    TRY(ensure_source_index(f, s));
+    double *sums;
+    TRY(ensure_t(f->ws[W_EMSUM], f->Q, s, &sums));
+    hipLaunchKernelGGL(em_source_sums, dim3(grid_for((int64_t)f->Q * 64, 256, 65535)), dim3(256), 0, s,
+                       (const int32_t *)f->em_order, (const int64_t *)f->em_start, f->Q, counts, smoothing, sums);
+    hipLaunchKernelGGL(em_normalize, dim3(grid_for(f->A, 256, 16384)), dim3(256), 0, s, (const int32_t *)f->em_src,
+                       f->A, counts, smoothing, (const double *)sums, cur_score, new_score);
+    HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 

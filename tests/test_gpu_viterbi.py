@@ -166,3 +166,17 @@ def test_config2_full(wf):
     d = wf.Fst.from_synth(fst)
     say("case: config2 full: decoding + oracle")
     assert_viterbi_parity(fst, batch, d, "config2 full")
+
+
+def test_att_fig1_output_string(wf):
+    """Figure 1 read from AT&T text, decoded on the GPU: the best path's
+    output symbols (looked up from best_olabels) are the figure's."""
+    from test_att_reader import fig1_att
+    text, isyms, osyms = fig1_att()
+    f = wf.read_att(text, isyms, osyms)
+    d = wf.Fst.from_synth(f)
+    toks = f.encode(["le", "chat", "</s>"])
+    score, arcs, status, ol = (x.cpu().numpy() for x in wf.viterbi(d, np.array([0, 3]), toks, olabels=True))
+    assert status[0] == 0 and list(arcs) == [0, 2, 4]
+    assert f.output_strings(ol, np.array([0, 3])) == [["the", "cat", "</s>"]]
+    assert score[0] == np.float32(np.log(np.float64(0.48)))  # the cost, rounded once to FP32
