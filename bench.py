@@ -108,7 +108,7 @@ def kernel_table(prof, bytes_per, steps, traffic=None, fused_counts=False):
         by["counts"] = 0.0
     kernels = {}
     for k, (ms, n) in prof.items():
-        if n == 0:
+        if n == 0 or k not in by:
             continue
         npass = passes[k] * steps
         avg = ms / npass
@@ -377,6 +377,11 @@ def main():
         _, b3 = synth.config(3)
         off3, tok3 = to_dev(b3)
         th3 = torch.tensor(fst.arc_score, device=dev, requires_grad=True)
+        d.set_scores(th3.detach())
+        tune3 = d.autotune(off3, tok3)
+        log(f"  autotune: {tune3['threads_per_sentence']} threads per sentence, {tune3['count_path']} counts; "
+            f"{tune3['best_ms']} ms per pass")
+        tune3 = {k: v for k, v in tune3.items() if k != "times"}
 
         def train_step():
             th3.grad = None
@@ -390,6 +395,7 @@ def main():
                                 "(lognormal lengths mean 25 in [5,60]); loss = sum of log Z; "
                                 "step = set_scores + forward + backward with expected counts through "
                                 "torch.autograd (LogPartition)",
+                    "autotune": tune3,
                     "symbols_per_s": round(n3 / (ms3 * 1e-3), 1), "ms_per_step": round(ms3, 4),
                     "alg_bytes_per_step": total_alg,
                     "step_frac": round(total_alg / (ms3 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
@@ -432,6 +438,24 @@ def main():
             for g1 in graphs1:
                 g1.close()
             del graphs1
+        log("  one 200-token sentence: sequential forward sweep vs time-parallel scan (latency)")
+        lens4 = b4.lengths()
+        b200 = int(np.nonzero(lens4 == 200)[0][0])
+        o200 = torch.tensor([0, 200], dtype=torch.int32, device=dev)
+        t200 = tok4[int(b4.offsets[b200]):int(b4.offsets[b200]) + 200]
+        lat = {}
+        for name, fn in (("forward_sweep", lambda: wf.forward(d4, o200, t200)[2].free()),
+                         ("scan", lambda: wf.forward_scan(d4, o200, t200))):
+            for _ in range(3):
+                fn()
+            ts = []
+            for _ in range(20):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            lat[name + "_us"] = round(sorted(ts)[len(ts) // 2] * 1e6, 1)
         graph4 = {"batched_viterbi_plus_fwd_bwd_symbols_per_s": round(n4 / (ms_g4 * 1e-3), 1),
                   "batched_ms_per_replay": round(ms_g4, 4),
                   "per_sentence_graph_viterbi_symbols_per_s": round(ps4["symbols"] / tg1["viterbi"], 1),
@@ -442,6 +466,7 @@ def main():
                               f"{b4.size} sentences, {int(b4.offsets[-1])} symbols (lengths uniform 1..200)",
                   "autotune": tune4,
                   "batched": rates4, "per_sentence": ps4, "graphs": graph4,
+                  "latency_one_sentence_T200": lat,
                   "batched_over_per_sentence": {
                       "viterbi": round(rates4["viterbi_symbols_per_s"] / ps4["viterbi_symbols_per_s"], 1),
                       "fwd_bwd": round(rates4["fwd_bwd_symbols_per_s"] / ps4["fwd_bwd_symbols_per_s"], 1)},

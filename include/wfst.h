@@ -156,7 +156,8 @@ int wfst_fst_label_stats(const wfst_fst *fst, int32_t *arcs, int32_t *fwd_segmen
 #define WFST_KERNEL_COUNTS 3     /* expected counts by label group */
 #define WFST_KERNEL_SCORES 4     /* score scatter of wfst_fst_set_scores (both layouts) */
 #define WFST_KERNEL_GRAD_FILL 5  /* zero fill of the gradient */
-#define WFST_KERNEL_COUNT 6
+#define WFST_KERNEL_SCAN 6       /* time-parallel scan (all its launches) */
+#define WFST_KERNEL_COUNT 7
 int wfst_fst_profile(wfst_fst *fst, int32_t enable);
 int wfst_fst_profile_read(wfst_fst *fst, double *ms, int64_t *launches, int32_t reset);
 
@@ -298,6 +299,29 @@ typedef struct wfst_autotune_result {
 int wfst_fst_autotune(wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
                       const int32_t *tokens, const char *cache_path, int32_t flags,
                       wfst_autotune_result *result, void *stream);
+
+/*
+ * Forward pass as a time-parallel scan (paper, section 6.1: the product of
+ * Eq. 1 is associative, so a parallel prefix computes it in log T depth;
+ * the paper leaves this to future work).  For FSTs with at most 64 states:
+ * every token's delta[w_t] becomes a dense |Q| x |Q| log-semiring matrix
+ * (parallel arcs log-added in arc-id order), and an inclusive scan over each
+ * sentence's matrices (ceil(log2 T_max) levels, each a matrix product per
+ * token, every entry a log-sum-exp over the inner index in increasing order)
+ * gives the prefix products P_t = delta[w_1] ... delta[w_t].  With the
+ * one-hot start vector, log alpha_t = row `start` of P_t and
+ * log Z = log sum_q exp(P_T[start][q] + final[q]) (FP64 accumulation).
+ * This is the latency path: depth log T instead of T, at |Q|^3 work per
+ * product and two matrices per token (at most 32 GiB); the sweeps of
+ * wfst_forward are the throughput path.
+ *   log_z float[batch], status int32[batch]: as wfst_forward (DEVICE).
+ *   alpha: NULL or DEVICE float[num_tokens * num_states]: row i = log alpha
+ *     after token i (unnormalised, natural log).
+ * Errors: WFST_EUNSUPPORTED for num_states > 64 or a batch beyond the matrix
+ * budget.  Reads back the longest sentence length (synchronises the stream).
+ */
+int wfst_forward_scan(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                      const int32_t *tokens, float *log_z, float *alpha, int32_t *status, void *stream);
 
 /*
  * EM M-step (paper, section 4: the expected counts of Algorithm 2 serve

@@ -18,7 +18,8 @@ import os
 import numpy as np
 
 __all__ = [
-    "WfstError", "Fst", "Tape", "Graph", "viterbi", "viterbi_noalloc", "forward", "backward", "forward_backward",
+    "WfstError", "Fst", "Tape", "Graph", "viterbi", "viterbi_noalloc", "forward", "forward_scan", "backward",
+    "forward_backward",
     "LogPartition", "log_partition", "em_update", "em_step", "read_att", "AttFst", "load_library", "layout_host", "library_path",
     "STATUS_OK", "STATUS_NO_PATH", "STATUS_BAD_TOKEN", "STATUS_BAD_INPUT",
 ]
@@ -83,7 +84,7 @@ EXPORTS = (
     "wfst_viterbi", "wfst_forward", "wfst_backward", "wfst_tape_free",
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
     "wfst_fst_score_version", "wfst_viterbi_noalloc", "wfst_graph_create", "wfst_graph_launch",
-    "wfst_graph_destroy", "wfst_em_update", "wfst_att_parse", "wfst_att_last_error",
+    "wfst_graph_destroy", "wfst_em_update", "wfst_att_parse", "wfst_att_last_error", "wfst_forward_scan",
 )
 
 
@@ -124,6 +125,7 @@ def load_library(path: str | None = None):
     lib.wfst_graph_destroy.argtypes = [P]
     lib.wfst_graph_destroy.restype = None
     lib.wfst_em_update.argtypes = [P, P, ctypes.c_float, P, P, P]
+    lib.wfst_forward_scan.argtypes = [P, i32, i64, P, P, P, P, P, P]
     lib.wfst_att_parse.argtypes = [ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.c_char_p, i64, i32, P,
                                    P, P, P, P, P, P]
     lib.wfst_att_parse.restype = ctypes.c_int
@@ -133,7 +135,8 @@ def load_library(path: str | None = None):
                  "wfst_fst_score_version", "wfst_fst_profile", "wfst_fst_profile_read",
                  "wfst_fst_label_stats", "wfst_viterbi", "wfst_viterbi_noalloc",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
-                 "wfst_fst_autotune", "wfst_graph_create", "wfst_graph_launch", "wfst_em_update"):
+                 "wfst_fst_autotune", "wfst_graph_create", "wfst_graph_launch", "wfst_em_update",
+                 "wfst_forward_scan"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -218,7 +221,7 @@ class Fst:
         _check(_lib.wfst_fst_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
 
-    KERNELS = ("viterbi", "forward", "backward", "counts", "scores", "grad_fill")
+    KERNELS = ("viterbi", "forward", "backward", "counts", "scores", "grad_fill", "scan")
 
     def label_stats(self):
         """(arcs, forward segments, reverse segments) per input label, int32 numpy arrays."""
@@ -393,6 +396,19 @@ def backward(fst: Fst, tape: Tape, grad_log_z=None, final=False):
         g = grad_log_z.to(dtype=torch.float32).contiguous()
     _check(_lib.wfst_backward(fst.handle, tape._h, _dptr(g), _dptr(grad), _dptr(gfin), _stream()))
     return (grad, gfin) if final else grad
+
+
+def forward_scan(fst: Fst, offsets, tokens, alpha: bool = False):
+    """log Z per sentence by the time-parallel scan (FSTs of at most 64 states):
+    (log_z f32[B], status i32[B][, log alpha f32[N, num_states] after each token])."""
+    import torch
+    off, tok, B, N = _batch(offsets, tokens)
+    log_z = torch.empty(B, dtype=torch.float32, device=off.device)
+    status = torch.empty(B, dtype=torch.int32, device=off.device)
+    al = torch.empty((N, fst.num_states), dtype=torch.float32, device=off.device) if alpha else None
+    _check(_lib.wfst_forward_scan(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(log_z), _dptr(al),
+                                  _dptr(status), _stream()))
+    return (log_z, status, al) if alpha else (log_z, status)
 
 
 def forward_backward(fst: Fst, offsets, tokens, final_posteriors=False):

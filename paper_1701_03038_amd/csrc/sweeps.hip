@@ -1978,6 +1978,175 @@ __global__ void fx_to_grad(const unsigned long long *__restrict__ acc, int64_t n
         grad[i] = (float)((double)(long long)acc[i] * inv);
 }
 
+// =====================================================================
+// Time-parallel scan of the forward pass over the per-token transition
+// matrices (Eq. 1 as a product of delta[w_t], evaluated as a parallel
+// prefix; for FSTs with at most kScanMaxQ states).  Dense |Q| x |Q| matrices
+// in the log semiring, -inf for no arc, row = source, column = destination.
+// =====================================================================
+constexpr int kScanMaxQ = 64;
+constexpr int kScanThreadsPerMat = 256;
+
+// log(e^a + e^b), exact for -inf operands
+__device__ __forceinline__ float log_add(float a, float b)
+{
+    const float m = fmaxf(a, b);
+    if (m == WFST_NINF) return WFST_NINF;
+    return m + log_e(exp_e(a - m) + exp_e(b - m));
+}
+
+// first token index of the sentence of every token
+__global__ void token_first(const int32_t *__restrict__ offsets, int32_t B, int64_t N, int32_t *__restrict__ first)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = B;  // last b with offsets[b] <= i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (offsets[mid] <= i) lo = mid; else hi = mid;
+        }
+        first[i] = offsets[lo];
+    }
+}
+
+// The matrix of every token's label: one workgroup per token; a thread owns
+// whole destination segments (columns), so parallel arcs of one (source,
+// destination) pair are log-added by one thread in arc-id order.
+__global__ void __launch_bounds__(kScanThreadsPerMat)
+scan_leaves(DevLayout fl, int32_t Q, const int32_t *__restrict__ tokens, int64_t N, int32_t M, float *__restrict__ P)
+{
+    const int64_t QQ = (int64_t)Q * Q;
+    for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
+        float *m = P + i * QQ;
+        for (int64_t e = threadIdx.x; e < QQ; e += blockDim.x) m[e] = WFST_NINF;
+        __syncthreads();
+        const int a = tokens[i];
+        if (a >= 0 && a < M) {
+            const LabelInfo li = fl.label[a];
+            for (int j = threadIdx.x; j < li.n_segs; j += blockDim.x) {
+                const int d = fl.seg_key[li.seg_first + j];
+                int c0 = li.n_slots + (j - li.n_multi), nc = 1;
+                if (j < li.n_multi) {
+                    const SegChunk sc = fl.seg_chunk[li.seg_first + j];
+                    c0 = sc.first;
+                    nc = sc.count;
+                }
+                for (int c = c0; c < c0 + nc; ++c) {
+                    const SliceInfo si = fl.slice[li.slice_first + (c >> 6)];
+                    for (int r = 0; r < si.height; ++r) {
+                        const int e = si.base + r * si.width + (c & 63);
+                        const int sq = fl.other[e];
+                        if (sq >= Q) continue;  // padding
+                        float &x = m[(int64_t)sq * Q + d];
+                        x = log_add(x, fl.score[e]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One level of the inclusive scan: out[i] = in[i - stride] (x) in[i] when
+// token i is at least `stride` tokens into its sentence, else in[i].  One
+// workgroup per token; both operands staged in LDS; every output element is
+// a two-pass log-sum-exp over k in increasing order.
+__global__ void __launch_bounds__(kScanThreadsPerMat)
+scan_level(const float *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ first, int64_t N,
+           int32_t Q, int32_t stride)
+{
+    __shared__ float A[kScanMaxQ * kScanMaxQ], Bm[kScanMaxQ * kScanMaxQ];
+    const int QQ = Q * Q;
+    for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
+        const float *b = in + i * (int64_t)QQ;
+        float *o = out + i * (int64_t)QQ;
+        if (i - first[i] < stride) {
+            for (int e = threadIdx.x; e < QQ; e += blockDim.x) o[e] = b[e];
+            continue;
+        }
+        const float *a = in + (i - stride) * (int64_t)QQ;
+        __syncthreads();  // the previous token's products are done reading A, Bm
+        for (int e = threadIdx.x; e < QQ; e += blockDim.x) {
+            A[e] = a[e];
+            Bm[e] = b[e];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < QQ; e += blockDim.x) {
+            const int r = e / Q, c = e - r * Q;
+            float m = WFST_NINF;
+            for (int k = 0; k < Q; ++k) m = fmaxf(m, A[r * Q + k] + Bm[k * Q + c]);
+            float v = WFST_NINF;
+            if (m != WFST_NINF) {
+                float sum = 0.0f;
+                for (int k = 0; k < Q; ++k) sum += exp_e((A[r * Q + k] + Bm[k * Q + c]) - m);
+                v = m + log_e(sum);
+            }
+            o[e] = v;
+        }
+    }
+}
+
+// Per sentence (one wavefront): status, log Z = LSE_q(P_T[start][q] + f[q])
+// (FP64 accumulation), and optionally log alpha_t = row `start` of each
+// prefix product (the start vector is one-hot).
+__global__ void scan_finish(const float *__restrict__ P, const int32_t *__restrict__ offsets,
+                           const int32_t *__restrict__ tokens, int32_t B, int64_t N, int32_t M, int32_t Q,
+                           int32_t start, const float *__restrict__ final_score, float *__restrict__ log_z,
+                           float *__restrict__ alpha, int32_t *__restrict__ status)
+{
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x / 64;
+    const int64_t QQ = (int64_t)Q * Q;
+    for (int b = blockIdx.x * wpb + (threadIdx.x >> 6); b < B; b += gridDim.x * wpb) {
+        const int o0 = offsets[b], o1 = offsets[b + 1];
+        if (o0 < 0 || o1 < o0 || (int64_t)o1 > N) {
+            if (lane == 0) {
+                status[b] = WFST_STATUS_BAD_INPUT;
+                log_z[b] = WFST_NINF;
+            }
+            continue;
+        }
+        int bad = 0;
+        for (int i = o0 + lane; i < o1; i += 64) bad |= tokens[i] < 0 || tokens[i] >= M;
+        if (__any(bad)) {
+            if (lane == 0) {
+                status[b] = WFST_STATUS_BAD_TOKEN;
+                log_z[b] = WFST_NINF;
+            }
+            continue;
+        }
+        if (alpha)
+            for (int64_t x = lane; x < (int64_t)(o1 - o0) * Q; x += 64) {
+                const int64_t i = o0 + x / Q;
+                const int q = (int)(x % Q);
+                alpha[i * Q + q] = P[i * QQ + (int64_t)start * Q + q];
+            }
+        double m = -__builtin_huge_val();
+        double v[2] = {-__builtin_huge_val(), -__builtin_huge_val()};
+        for (int u = 0; u < 2; ++u) {
+            const int q = lane + 64 * u;
+            if (q < Q) {
+                const float x = o1 > o0 ? P[(int64_t)(o1 - 1) * QQ + (int64_t)start * Q + q] : (q == start ? 0.0f : WFST_NINF);
+                const float f = final_score[q];
+                if (x != WFST_NINF && f != WFST_NINF) v[u] = (double)x + (double)f;
+            }
+            m = fmax(m, v[u]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        double sum = 0.0;
+        if (m != -__builtin_huge_val())
+            for (int u = 0; u < 2; ++u)
+                if (v[u] != -__builtin_huge_val()) sum += exp(v[u] - m);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == 0) {
+            const bool ok = m != -__builtin_huge_val();
+            status[b] = ok ? WFST_STATUS_OK : WFST_STATUS_NO_PATH;
+            log_z[b] = ok ? (float)(m + log(sum)) : WFST_NINF;
+        }
+    }
+}
+
 // EM M-step, per-state totals: one wavefront per source state; lane l sums
 // the state's arcs l, l + 64, ... in order in FP64, then a fixed butterfly
 // combines the lanes, so the total has the same bits on every call.

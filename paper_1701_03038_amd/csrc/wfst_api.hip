@@ -95,12 +95,16 @@ enum WsSlot {
     W_ORDER, W_TOKOFF, W_TILES, W_COUNTERS, W_BP, W_PATH, W_BETA, W_BMAX, W_BLOG, W_LZB, W_TOKSENT,
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
-    W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_NUM
+    W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_SCAN0,
+    W_SCAN1, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
 // not fit on chip: at most this many bytes (the persistent grid shrinks to fit).
 constexpr int64_t kStateScratchBudget = (int64_t)16 << 30;
+
+// Matrices of the time-parallel scan: at most this many bytes (two per token).
+constexpr int64_t kScanBudgetBytes = (int64_t)32 << 30;
 
 // small device counters kept together (one allocation)
 enum Counter { C_QUEUE = 0, C_NITEMS = 1, C_SLOTS = 2, C_ITEMQ = 3, C_TOTAL = 4 /* int64 at byte 16 */,
@@ -1860,6 +1864,52 @@ int wfst_fst_autotune(wfst_fst *f, int32_t batch, int64_t num_tokens, const int3
         TRY(write_tune_cache(cache_path, cache));
     }
     if (res) *res = r;
+    return WFST_OK;
+}
+
+int wfst_forward_scan(const wfst_fst *fc, int32_t batch, int64_t num_tokens, const int32_t *offsets,
+                      const int32_t *tokens, float *log_z, float *alpha, int32_t *status, void *stream)
+{
+    TRY(check_batch(fc, batch, num_tokens, offsets, tokens));
+    if (batch == 0) return WFST_OK;
+    if (!log_z || !status) return set_err(WFST_EINVAL, "NULL output");
+    wfst_fst *f = const_cast<wfst_fst *>(fc);
+    if (f->Q > kScanMaxQ)
+        return set_err(WFST_EUNSUPPORTED, "the scan keeps dense state x state matrices: num_states must be <= " +
+                                              std::to_string(kScanMaxQ));
+    hipStream_t s = as_stream(stream);
+    const int64_t N = num_tokens, QQ = (int64_t)f->Q * f->Q;
+    if ((double)N * (double)QQ * 2.0 * sizeof(float) > (double)kScanBudgetBytes)
+        return set_err(WFST_EUNSUPPORTED, "the scan needs two state x state matrices per token: " +
+                                              std::to_string(N) + " tokens exceed its " +
+                                              std::to_string(kScanBudgetBytes >> 30) + " GiB");
+    int32_t *counters = nullptr, *first = nullptr;
+    float *p0 = nullptr, *p1 = nullptr;
+    TRY(ensure_t(f->ws[W_COUNTERS], C_COUNT, s, &counters));
+    int32_t tmax = 0;
+    if (N > 0) {
+        TRY(ensure_t(f->ws[W_TOKSENT], N, s, &first));
+        TRY(ensure_t(f->ws[W_SCAN0], N * QQ, s, &p0));
+        TRY(ensure_t(f->ws[W_SCAN1], N * QQ, s, &p1));
+        // longest sentence: the number of levels (one read-back; the scan is the latency path)
+        hipLaunchKernelGGL(batch_max_len, dim3(1), dim3(1024), 0, s, offsets, batch, counters + C_TOTAL);
+        HIP_OK(hipMemcpyAsync(&tmax, counters + C_TOTAL, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    ProfScope prof(f, s, WFST_KERNEL_SCAN);
+    if (N > 0) {
+        hipLaunchKernelGGL(token_first, dim3(grid_for(N, 256)), dim3(256), 0, s, offsets, batch, N, first);
+        const unsigned g = (unsigned)std::min<int64_t>(N, 65535);
+        hipLaunchKernelGGL(scan_leaves, dim3(g), dim3(kScanThreadsPerMat), 0, s, f->fwd, f->Q, tokens, N, f->M, p0);
+        for (int64_t stride = 1; stride < tmax; stride *= 2) {
+            hipLaunchKernelGGL(scan_level, dim3(g), dim3(kScanThreadsPerMat), 0, s, (const float *)p0, p1,
+                               (const int32_t *)first, N, f->Q, (int32_t)stride);
+            std::swap(p0, p1);
+        }
+    }
+    hipLaunchKernelGGL(scan_finish, dim3(grid_for(batch, 4)), dim3(256), 0, s, (const float *)p0, offsets, tokens,
+                       batch, N, f->M, f->Q, f->start, (const float *)f->final_score, log_z, alpha, status);
+    HIP_OK(hipGetLastError());
     return WFST_OK;
 }
 
