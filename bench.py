@@ -302,8 +302,9 @@ def main():
                     help="workgroup size per sentence of the sweeps (64..1024; 0: library default)")
     ap.add_argument("--powerlaw-steps", type=int, default=2,
                     help="timed training steps on the 1M-state power-law workload (0: skip)")
-    ap.add_argument("--only-main", action="store_true",
-                    help="time only the main workload (for profiler runs)")
+    ap.add_argument("--workloads", default="main,training,bigram,powerlaw",
+                    help="comma-separated lines to run besides the main step (training, bigram, powerlaw); "
+                         "the main workload always runs (for profiler runs: --workloads main)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -366,13 +367,14 @@ def main():
     roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
 
     per_sentence = None
-    if args.per_sentence > 0 and not args.only_main:
+    want = set(args.workloads.split(","))
+    if args.per_sentence > 0 and "main" in want:
         P = min(args.per_sentence, batch.size)
         log(f"per-sentence form on {P} sentences (one call per sentence)")
         per_sentence = per_sentence_rates(wf, d, batch, off, tok, P)
 
     training = None
-    if not args.only_main:
+    if "training" in want:
         log("training step on the 1024-sentence batch (LogPartition forward + backward)")
         _, b3 = synth.config(3)
         off3, tok3 = to_dev(b3)
@@ -403,7 +405,7 @@ def main():
         del b3, off3, tok3, th3
 
     bigram = None
-    if not args.only_main:
+    if "bigram" in want:
         log("bigram tagger (vocabulary 200k), 16384 sentences of length 1..200")
         f4, b4 = synth.config(4)
         d4 = wf.Fst.from_synth(f4)
@@ -475,7 +477,7 @@ def main():
         del f4, b4, d4
 
     powerlaw = None
-    if not args.only_main and args.powerlaw_steps > 0:
+    if "powerlaw" in want and args.powerlaw_steps > 0:
         log("power-law WFST: 1M states, 50M arcs, 1024 random-walk strings of 100")
         t = time.time()
         f5, b5 = synth.config(5)
@@ -520,7 +522,7 @@ def main():
         sample = min(args.cpu_sample, batch.size)
         log(f"CPU oracle on {sample} sentences, one thread")
         cpu = cpu_baseline(fst, batch, sample)
-        if not args.only_main:
+        if "main" in want:
             nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
             log(f"CPU oracle on {sample} sentences, {nth} threads")
             cpu_mt = cpu_baseline(fst, batch, sample, threads=nth)
