@@ -157,7 +157,8 @@ int wfst_fst_label_stats(const wfst_fst *fst, int32_t *arcs, int32_t *fwd_segmen
 #define WFST_KERNEL_SCORES 4     /* score scatter of wfst_fst_set_scores (both layouts) */
 #define WFST_KERNEL_GRAD_FILL 5  /* zero fill of the gradient */
 #define WFST_KERNEL_SCAN 6       /* time-parallel scan (all its launches) */
-#define WFST_KERNEL_COUNT 7
+#define WFST_KERNEL_LATTICE 7    /* forward pass over input lattices */
+#define WFST_KERNEL_COUNT 8
 int wfst_fst_profile(wfst_fst *fst, int32_t enable);
 int wfst_fst_profile_read(wfst_fst *fst, double *ms, int64_t *launches, int32_t reset);
 
@@ -322,6 +323,44 @@ int wfst_fst_autotune(wfst_fst *fst, int32_t batch, int64_t num_tokens, const in
  */
 int wfst_forward_scan(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const int32_t *offsets,
                       const int32_t *tokens, float *log_z, float *alpha, int32_t *status, void *stream);
+
+/*
+ * Forward pass over input lattices: the FST composed with an acyclic weighted
+ * acceptor over input labels instead of a string (paper, section 6.1 names
+ * input lattices as the case the prefix-sum scan does not cover; section 3
+ * rules out epsilon transitions in the FST, which stays so: epsilon here is
+ * on lattice arcs only).  Lattice b has nodes node_offsets[b] ..
+ * node_offsets[b+1]-1 (local ids 0..n_b-1, in topological order; local 0 is
+ * the start node, n_b-1 the end node) and arcs arc_offsets[b] ..
+ * arc_offsets[b+1]-1, each (from, to, label, weight) with local node ids,
+ * from < to, label in [0, num_input_labels) or -1 for epsilon, weight a
+ * natural-log score (-inf = disabled arc), and the arcs of a lattice sorted by
+ * `to` (stable order among equal `to` is the summation order).  With A_0 the
+ * one-hot vector of the FST's start state and, for node v, in arc order,
+ *   A_v = log-sum over incoming arcs (u, v, a, w) of
+ *         (A_u (x) delta[a]) + w   (Eq. 1 in the log semiring), or A_u + w for epsilon,
+ *   log Z_b = log sum_q exp(A_{n_b-1}[q] + final[q]).
+ * A string w_1..w_T is the chain lattice 0 -w_1-> 1 ... -w_T-> T with zero
+ * weights, for which this equals wfst_forward.  One persistent workgroup per
+ * lattice; the node vectors are kept normalised (FP32 with an FP64 scale per
+ * node) and incoming contributions are log-added in FP64 on chip.
+ *   node_offsets, arc_offsets: DEVICE int32[batch + 1], non-decreasing, every
+ *     lattice with at least one node.
+ *   arc_from, arc_to, arc_label: DEVICE int32[num_arcs]; arc_weight DEVICE float[num_arcs].
+ *   log_z: DEVICE float[batch]; status: DEVICE int32[batch] (WFST_STATUS_*:
+ *     BAD_INPUT for a malformed lattice or non-monotone offsets anywhere in
+ *     the batch, BAD_TOKEN for a label out of range, NO_PATH when nothing
+ *     reaches a final state; log_z = -inf in all of these).
+ *   node_log_alpha: NULL or DEVICE float[num_nodes * num_states]: A_v per node
+ *     (natural log, unnormalised).
+ * Errors: WFST_EINVAL for negative sizes or NULL buffers; WFST_EUNSUPPORTED
+ * when the FST's state vector and its largest label's segments do not fit
+ * the on-chip accumulator.  Does not synchronise the stream.
+ */
+int wfst_lattice_forward(const wfst_fst *fst, int32_t batch, const int32_t *node_offsets,
+                         const int32_t *arc_offsets, int64_t num_nodes, int64_t num_arcs, const int32_t *arc_from,
+                         const int32_t *arc_to, const int32_t *arc_label, const float *arc_weight, float *log_z,
+                         float *node_log_alpha, int32_t *status, void *stream);
 
 /*
  * EM M-step (paper, section 4: the expected counts of Algorithm 2 serve

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "WfstError", "Fst", "Tape", "Graph", "viterbi", "viterbi_noalloc", "forward", "forward_scan", "backward",
-    "forward_backward",
+    "forward_backward", "lattice_forward", "lattices_from_lists",
     "LogPartition", "log_partition", "em_update", "em_step", "read_att", "AttFst", "load_library", "layout_host", "library_path",
     "STATUS_OK", "STATUS_NO_PATH", "STATUS_BAD_TOKEN", "STATUS_BAD_INPUT",
 ]
@@ -85,6 +85,7 @@ EXPORTS = (
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
     "wfst_fst_score_version", "wfst_viterbi_noalloc", "wfst_graph_create", "wfst_graph_launch",
     "wfst_graph_destroy", "wfst_em_update", "wfst_att_parse", "wfst_att_last_error", "wfst_forward_scan",
+    "wfst_lattice_forward",
 )
 
 
@@ -126,6 +127,7 @@ def load_library(path: str | None = None):
     lib.wfst_graph_destroy.restype = None
     lib.wfst_em_update.argtypes = [P, P, ctypes.c_float, P, P, P]
     lib.wfst_forward_scan.argtypes = [P, i32, i64, P, P, P, P, P, P]
+    lib.wfst_lattice_forward.argtypes = [P, i32, P, P, i64, i64, P, P, P, P, P, P, P, P]
     lib.wfst_att_parse.argtypes = [ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.c_char_p, i64, i32, P,
                                    P, P, P, P, P, P]
     lib.wfst_att_parse.restype = ctypes.c_int
@@ -136,7 +138,7 @@ def load_library(path: str | None = None):
                  "wfst_fst_label_stats", "wfst_viterbi", "wfst_viterbi_noalloc",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
                  "wfst_fst_autotune", "wfst_graph_create", "wfst_graph_launch", "wfst_em_update",
-                 "wfst_forward_scan"):
+                 "wfst_forward_scan", "wfst_lattice_forward"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -221,7 +223,7 @@ class Fst:
         _check(_lib.wfst_fst_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
 
-    KERNELS = ("viterbi", "forward", "backward", "counts", "scores", "grad_fill", "scan")
+    KERNELS = ("viterbi", "forward", "backward", "counts", "scores", "grad_fill", "scan", "lattice")
 
     def label_stats(self):
         """(arcs, forward segments, reverse segments) per input label, int32 numpy arrays."""
@@ -409,6 +411,55 @@ def forward_scan(fst: Fst, offsets, tokens, alpha: bool = False):
     _check(_lib.wfst_forward_scan(fst.handle, B, N, _dptr(off), _dptr(tok), _dptr(log_z), _dptr(al),
                                   _dptr(status), _stream()))
     return (log_z, status, al) if alpha else (log_z, status)
+
+
+def lattices_from_lists(lattices):
+    """Concatenate lattices given as (num_nodes, [(from, to, label, weight), ...])
+    (local node ids, label -1 = epsilon) into the flat arrays of
+    lattice_forward: node_offsets, arc_offsets, from, to, label, weight.
+    Arcs are stably sorted by target node."""
+    n_off = [0]
+    a_off = [0]
+    cols = ([], [], [], [])
+    for n, arcs in lattices:
+        arcs = sorted(arcs, key=lambda e: e[1])
+        for e in arcs:
+            for c, x in zip(cols, e):
+                c.append(x)
+        n_off.append(n_off[-1] + int(n))
+        a_off.append(a_off[-1] + len(arcs))
+    return (np.asarray(n_off, np.int32), np.asarray(a_off, np.int32), np.asarray(cols[0], np.int32),
+            np.asarray(cols[1], np.int32), np.asarray(cols[2], np.int32), np.asarray(cols[3], np.float32))
+
+
+def lattice_forward(fst: Fst, node_offsets, arc_offsets, arc_from, arc_to, arc_label, arc_weight,
+                    node_alpha: bool = False):
+    """log Z of the FST composed with each input lattice (wfst_lattice_forward):
+    (log_z f32[B], status i32[B][, log alpha f32[num_nodes, num_states] per node])."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+
+    def as_dev(x, dt):
+        if isinstance(x, torch.Tensor):
+            return x.to(device=dev, dtype=dt).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(x), device=dev).to(dt)
+
+    noff, aoff = as_dev(node_offsets, torch.int32), as_dev(arc_offsets, torch.int32)
+    fr, to, lab = as_dev(arc_from, torch.int32), as_dev(arc_to, torch.int32), as_dev(arc_label, torch.int32)
+    w = as_dev(arc_weight, torch.float32)
+    B = int(noff.shape[0]) - 1
+    if int(aoff.shape[0]) != B + 1:
+        raise WfstError(WFST_EINVAL, "node_offsets and arc_offsets differ in length")
+    E = int(fr.shape[0])
+    if not (int(to.shape[0]) == int(lab.shape[0]) == int(w.shape[0]) == E):
+        raise WfstError(WFST_EINVAL, "arc arrays differ in length")
+    V = int(noff[-1].item()) if B >= 0 and noff.numel() else 0
+    log_z = torch.empty(max(B, 0), dtype=torch.float32, device=dev)
+    status = torch.empty(max(B, 0), dtype=torch.int32, device=dev)
+    al = torch.empty((V, fst.num_states), dtype=torch.float32, device=dev) if node_alpha else None
+    _check(_lib.wfst_lattice_forward(fst.handle, B, _dptr(noff), _dptr(aoff), V, E, _dptr(fr), _dptr(to),
+                                     _dptr(lab), _dptr(w), _dptr(log_z), _dptr(al), _dptr(status), _stream()))
+    return (log_z, status, al) if node_alpha else (log_z, status)
 
 
 def forward_backward(fst: Fst, offsets, tokens, final_posteriors=False):

@@ -2147,6 +2147,172 @@ __global__ void scan_finish(const float *__restrict__ P, const int32_t *__restri
     }
 }
 
+// =====================================================================
+// Forward pass over input lattices (the input as an acyclic weighted
+// acceptor instead of a string; epsilon lattice arcs read no symbol).
+// Node v's vector is the log-sum over its incoming arcs (u, v, a, w), in
+// their order, of (A_u x delta[a]) + w, or A_u + w for epsilon; vectors are
+// kept normalised in FP32 with an FP64 scale per node.
+// =====================================================================
+__device__ __forceinline__ double log_add_d(double a, double b)
+{
+    const double m = fmax(a, b);
+    if (m == -__builtin_huge_val()) return m;
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+struct LatticeView {
+    int32_t B = 0;
+    int64_t n_nodes = 0, n_arcs = 0;
+    const int32_t *node_off = nullptr, *arc_off = nullptr;  // [B+1] each
+    const int32_t *from = nullptr, *to = nullptr, *label = nullptr;
+    const float *weight = nullptr;
+    float *nodes = nullptr;   // [n_nodes * (Q+1)] normalised vectors (entry Q = -inf)
+    double *scale = nullptr;  // [n_nodes]
+    int32_t *queue = nullptr;
+    const int32_t *offs_bad = nullptr;  // set by lattice_offsets_check
+};
+
+// Non-monotone offsets anywhere would let two lattices share node rows: one
+// flag for the whole batch, which every lattice then reports as BAD_INPUT.
+__global__ void lattice_offsets_check(const int32_t *__restrict__ node_off, const int32_t *__restrict__ arc_off,
+                                      int32_t B, int64_t n_nodes, int64_t n_arcs, int32_t *__restrict__ flag)
+{
+    bool bad = false;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b <= B; b += (int64_t)gridDim.x * blockDim.x) {
+        bad |= node_off[b] < 0 || (int64_t)node_off[b] > n_nodes || arc_off[b] < 0 || (int64_t)arc_off[b] > n_arcs;
+        if (b < B) bad |= node_off[b + 1] <= node_off[b] || arc_off[b + 1] < arc_off[b];
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+lattice_forward(DevLayout fl, int32_t Q, int32_t start, int32_t M, const float *__restrict__ final_score,
+                LatticeView lv, float *__restrict__ log_z, float *__restrict__ node_alpha,
+                int32_t *__restrict__ status, uint32_t *__restrict__ health)
+{
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *acc = reinterpret_cast<double *>(smem);         // [Q+1] node being built
+    double *vval = acc + (Q + 1);                             // [max_segs]
+    double *part = vval + max(fl.max_segs, 1);                // [max_slots]
+    int32_t *vkey = reinterpret_cast<int32_t *>(part + max(fl.max_slots, 1));  // [max_segs]
+    __shared__ int s_item;
+    __shared__ unsigned long long s_cmax;
+    __shared__ double s_rm[NW];
+    __shared__ float s_rs[NW];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+    const int64_t Q1 = (int64_t)Q + 1;
+
+    for (int pops = 0;; ++pops) {
+        if (tid == 0) s_item = atomicAdd(lv.queue, 1);
+        __syncthreads();
+        const int b = wave_uniform(s_item);
+        __syncthreads();
+        if (b >= lv.B) break;
+        if (b < 0 || pops > lv.B) {
+            if (tid == 0) atomicOr(health, H_QUEUE);
+            break;
+        }
+        const int n0 = lv.node_off[b], n1 = lv.node_off[b + 1];
+        const int a0 = lv.arc_off[b], a1 = lv.arc_off[b + 1];
+        const int n = n1 - n0;
+        int bad = (*lv.offs_bad || n0 < 0 || n < 1 || (int64_t)n1 > lv.n_nodes || a0 < 0 || a1 < a0 ||
+                   (int64_t)a1 > lv.n_arcs) ? 1 : 0;
+        int badtok = 0;
+        if (!bad)
+            for (int e = a0 + tid; e < a1; e += NT) {
+                const int u = lv.from[e], v = lv.to[e], a = lv.label[e];
+                const float w = lv.weight[e];
+                bad |= u < 0 || v <= u || v >= n || (e > a0 && lv.to[e - 1] > v) || isnan(w) || w == -WFST_NINF;
+                badtok |= a < -1 || a >= M;
+            }
+        bad = __syncthreads_or(bad);
+        badtok = __syncthreads_or(badtok);
+        if (bad || badtok) {
+            if (tid == 0) {
+                status[b] = bad ? WFST_STATUS_BAD_INPUT : WFST_STATUS_BAD_TOKEN;
+                log_z[b] = WFST_NINF;
+            }
+            continue;
+        }
+        for (int64_t q = tid; q < Q1; q += NT) lv.nodes[(int64_t)n0 * Q1 + q] = q == start ? 0.0f : WFST_NINF;
+        if (tid == 0) lv.scale[n0] = 0.0;
+        __syncthreads();
+        int e = a0;
+        for (int v = 1; v < n; ++v) {
+            for (int64_t q = tid; q < Q1; q += NT) acc[q] = -__builtin_huge_val();
+            if (tid == 0) s_cmax = 0ull;
+            __syncthreads();
+            for (; e < a1 && lv.to[e] == v; ++e) {  // incoming arcs, in their order
+                const int u = lv.from[e], a = lv.label[e];
+                const double w = (double)lv.weight[e];
+                const float *prev = lv.nodes + (int64_t)(n0 + u) * Q1;
+                const double cu = lv.scale[n0 + u] + w;
+                if (a < 0) {
+                    for (int q = tid; q < Q; q += NT) {
+                        const float x = prev[q];
+                        if (x != WFST_NINF) acc[q] = log_add_d(acc[q], (double)x + cu);
+                    }
+                } else {
+                    const LabelInfo li = uniform_label(fl.label[a]);
+                    (void)lse_step<NT, 8>(fl, li, prev, part, vval, vkey, lane, wave, Q);
+                    __syncthreads();
+                    for (int j = tid; j < li.n_segs; j += NT) {  // distinct keys: no two threads share one
+                        const double x = vval[j];
+                        if (x != -__builtin_huge_val()) acc[vkey[j]] = log_add_d(acc[vkey[j]], x + cu);
+                    }
+                }
+                __syncthreads();
+            }
+            double mx = -__builtin_huge_val();
+            for (int64_t q = tid; q < Q; q += NT) mx = fmax(mx, acc[q]);
+            block_max_d(mx, &s_cmax, lane);
+            __syncthreads();
+            double c = unord_f64(s_cmax);
+            if (!(c > -__builtin_huge_val())) c = 0.0;
+            float *node = lv.nodes + (int64_t)(n0 + v) * Q1;
+            for (int64_t q = tid; q < Q1; q += NT)
+                node[q] = acc[q] == -__builtin_huge_val() ? WFST_NINF : (float)(acc[q] - c);
+            if (tid == 0) lv.scale[n0 + v] = c;
+            __syncthreads();
+        }
+        if (node_alpha)
+            for (int64_t x = tid; x < (int64_t)n * Q; x += NT) {
+                const int64_t v = x / Q, q = x - v * Q;
+                const float y = lv.nodes[(n0 + v) * Q1 + q];
+                node_alpha[(n0 + v) * (int64_t)Q + q] =
+                    y == WFST_NINF ? WFST_NINF : (float)((double)y + lv.scale[n0 + v]);
+            }
+        // log Z = C_end + LSE_q(A^_end[q] + f[q])
+        const float *last = lv.nodes + (int64_t)(n1 - 1) * Q1;
+        LseD z{-__builtin_huge_val(), 0.0f};
+        for (int q = tid; q < Q; q += NT) {
+            const float x = last[q], f = final_score[q];
+            if (x == WFST_NINF || f == WFST_NINF) continue;
+            lse_push_d(z, (double)x + (double)f);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) z = lse_merge_d(z, LseD{__shfl_xor(z.m, o, 64), __shfl_xor(z.s, o, 64)});
+        if (lane == 0) {
+            s_rm[wave] = z.m;
+            s_rs[wave] = z.s;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            LseD tot{s_rm[0], s_rs[0]};
+            for (int w2 = 1; w2 < NW; ++w2) tot = lse_merge_d(tot, LseD{s_rm[w2], s_rs[w2]});
+            const double lzr = lse_value_d(tot);
+            const bool ok = lzr != -__builtin_huge_val();
+            status[b] = ok ? WFST_STATUS_OK : WFST_STATUS_NO_PATH;
+            log_z[b] = ok ? (float)(lv.scale[n1 - 1] + lzr) : WFST_NINF;
+        }
+        __syncthreads();
+    }
+}
+
 // EM M-step, per-state totals: one wavefront per source state; lane l sums
 // the state's arcs l, l + 64, ... in order in FP64, then a fixed butterfly
 // combines the lanes, so the total has the same bits on every call.

@@ -96,7 +96,7 @@ enum WsSlot {
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
     W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_SCAN0,
-    W_SCAN1, W_NUM
+    W_SCAN1, W_LATNODE, W_LATSCALE, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
@@ -1909,6 +1909,62 @@ int wfst_forward_scan(const wfst_fst *fc, int32_t batch, int64_t num_tokens, con
     }
     hipLaunchKernelGGL(scan_finish, dim3(grid_for(batch, 4)), dim3(256), 0, s, (const float *)p0, offsets, tokens,
                        batch, N, f->M, f->Q, f->start, (const float *)f->final_score, log_z, alpha, status);
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
+}
+
+size_t lds_lattice(const wfst_fst *f)
+{
+    return ((size_t)f->Q + 1 + (size_t)std::max(f->fwd.max_segs, 1) + (size_t)std::max(f->fwd.max_slots, 1)) *
+               sizeof(double) +
+           (size_t)std::max(f->fwd.max_segs, 1) * sizeof(int32_t);
+}
+
+int wfst_lattice_forward(const wfst_fst *fc, int32_t batch, const int32_t *node_offsets, const int32_t *arc_offsets,
+                         int64_t num_nodes, int64_t num_arcs, const int32_t *arc_from, const int32_t *arc_to,
+                         const int32_t *arc_label, const float *arc_weight, float *log_z, float *node_log_alpha,
+                         int32_t *status, void *stream)
+{
+    if (!fc) return set_err(WFST_EINVAL, "fst is NULL");
+    if (batch < 0 || num_nodes < 0 || num_arcs < 0) return set_err(WFST_EINVAL, "negative size");
+    if (num_nodes > INT32_MAX || num_arcs > INT32_MAX) return set_err(WFST_EINVAL, "lattice ids are int32");
+    if (batch == 0) return WFST_OK;
+    if (!node_offsets || !arc_offsets || !log_z || !status) return set_err(WFST_EINVAL, "NULL offsets or output");
+    if (num_arcs > 0 && (!arc_from || !arc_to || !arc_label || !arc_weight))
+        return set_err(WFST_EINVAL, "NULL arc array");
+    wfst_fst *f = const_cast<wfst_fst *>(fc);
+    hipStream_t s = as_stream(stream);
+    constexpr int NT = 256;
+    const size_t lds = lds_lattice(f);
+    int grid = 0;
+    TRY(persistent_grid(f, lattice_forward<NT>, NT, lds, batch, &grid));
+    int32_t *counters = nullptr;
+    float *nodes = nullptr;
+    double *scale = nullptr;
+    const int64_t Q1 = (int64_t)f->Q + 1;
+    TRY(ensure_t(f->ws[W_COUNTERS], C_COUNT, s, &counters));
+    TRY(ensure_t(f->ws[W_LATNODE], std::max<int64_t>(num_nodes, 1) * Q1, s, &nodes));
+    TRY(ensure_t(f->ws[W_LATSCALE], std::max<int64_t>(num_nodes, 1), s, &scale));
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
+    LatticeView lv;
+    lv.B = batch;
+    lv.n_nodes = num_nodes;
+    lv.n_arcs = num_arcs;
+    lv.node_off = node_offsets;
+    lv.arc_off = arc_offsets;
+    lv.from = arc_from;
+    lv.to = arc_to;
+    lv.label = arc_label;
+    lv.weight = arc_weight;
+    lv.nodes = nodes;
+    lv.scale = scale;
+    lv.queue = counters + C_QUEUE;
+    lv.offs_bad = counters + C_NITEMS;
+    hipLaunchKernelGGL(lattice_offsets_check, dim3(grid_for((int64_t)batch + 1, 256)), dim3(256), 0, s, node_offsets,
+                       arc_offsets, batch, num_nodes, num_arcs, counters + C_NITEMS);
+    ProfScope prof(f, s, WFST_KERNEL_LATTICE);
+    hipLaunchKernelGGL((lattice_forward<NT>), dim3(grid), dim3(NT), lds, s, f->fwd, f->Q, f->start, f->M,
+                       (const float *)f->final_score, lv, log_z, node_log_alpha, status, f->health);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }

@@ -23,7 +23,7 @@ import numpy as np
 __all__ = [
     "Fst", "Batch", "zipf_probs", "zipf_tokens", "lognormal_lengths",
     "tiny_random_fst", "random_batch", "hmm_bigram", "hmm_trigram",
-    "powerlaw_fst", "random_walk_batch", "config",
+    "powerlaw_fst", "random_walk_batch", "config", "random_lattice", "confusion_network",
 ]
 
 
@@ -360,3 +360,39 @@ def config(i: int, seed: int = 0, **kw):
         b.meta["config"] = 5
         return fst, b
     raise ValueError(f"unknown configuration {i}")
+
+
+def random_lattice(seed: int, num_ilabels: int, n_nodes: int, n_arcs: int, eps: float = 0.2) -> list:
+    """An acyclic input lattice as arcs (from, to, label, log weight): nodes in
+    topological order, one arc into every node from an earlier one (so every
+    node is reachable from node 0), then n_arcs random forward arcs; label -1
+    (epsilon) with probability eps; weights log U(0.2, 1)."""
+    rng = np.random.default_rng(seed)
+    arcs = []
+    for v in range(1, n_nodes):
+        arcs.append((int(rng.integers(0, v)), v, int(rng.integers(0, num_ilabels)),
+                     float(np.log(rng.uniform(0.2, 1.0)))))
+    for _ in range(n_arcs):
+        u = int(rng.integers(0, n_nodes - 1))
+        v = int(rng.integers(u + 1, n_nodes))
+        a = -1 if rng.random() < eps else int(rng.integers(0, num_ilabels))
+        arcs.append((u, v, a, float(np.log(rng.uniform(0.2, 1.0)))))
+    return arcs
+
+
+def confusion_network(seed: int, tokens, num_ilabels: int, alternatives: int = 3, zipf_s: float = 1.1,
+                      deletion: float = 0.1) -> tuple[int, list]:
+    """A confusion network ("sausage") around a token sequence, the usual
+    shape of a recogniser's output lattice: node t -> t+1 carries the token
+    and `alternatives` Zipf-drawn competitors, and with probability `deletion`
+    an epsilon arc; the slot's weights are the logs of a Dirichlet(1) draw.
+    Returns (num_nodes, arcs)."""
+    rng = np.random.default_rng(seed)
+    arcs = []
+    for t, w in enumerate(np.asarray(tokens)):
+        labels = [int(w)] + [int(x) for x in zipf_tokens(rng, num_ilabels, zipf_s, alternatives)]
+        if rng.random() < deletion:
+            labels.append(-1)
+        p = rng.dirichlet(np.ones(len(labels)))
+        arcs += [(t, t + 1, a, float(np.log(max(pi, 1e-30)))) for a, pi in zip(labels, p)]
+    return len(tokens) + 1, arcs
