@@ -87,6 +87,17 @@ def algorithmic_bytes(fst_dev, batch, Q=None):
     return out
 
 
+def lattice_bytes(fst_dev, Q, n_nodes, labels):
+    """Bytes the method moves in one lattice pass: per labelled lattice arc
+    the label's arcs and segments (8 A_a + 8 D_a, as a string step), per
+    lattice arc (epsilon included) its source node's vector (4 Q), per node
+    its vector written once (4 Q)."""
+    import numpy as np
+    arcs, dseg, _ = (x.astype(np.int64) for x in fst_dev.label_stats())
+    lab = labels[labels >= 0]
+    return float((8 * arcs[lab] + 8 * dseg[lab]).sum() + 4 * Q * labels.size + 4 * Q * n_nodes)
+
+
 def kernel_table(prof, bytes_per, steps, traffic=None, fused_counts=False):
     """Per kernel kind: ms per pass over the batch (HIP events on the call
     stream, summed over the pass's launches), the method's bytes per pass,
@@ -302,8 +313,9 @@ def main():
                     help="workgroup size per sentence of the sweeps (64..1024; 0: library default)")
     ap.add_argument("--powerlaw-steps", type=int, default=2,
                     help="timed training steps on the 1M-state power-law workload (0: skip)")
-    ap.add_argument("--workloads", default="main,training,bigram,powerlaw",
-                    help="comma-separated lines to run besides the main step (training, bigram, powerlaw); "
+    ap.add_argument("--workloads", default="main,training,lattice,bigram,powerlaw",
+                    help="comma-separated lines to run besides the main step (training, lattice, bigram, "
+                         "powerlaw); "
                          "the main workload always runs (for profiler runs: --workloads main)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counter scaling)")
@@ -403,6 +415,33 @@ def main():
                     "step_frac": round(total_alg / (ms3 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                     "roofline": roofline_of(k3), "kernels": k3}
         del b3, off3, tok3, th3
+
+    lattice = None
+    if "lattice" in want:
+        log("input lattices: confusion networks around the 4096 sentences, trigram tagger WFST")
+        t = time.time()
+        nets = [synth.confusion_network(1000 + b, batch.sentence(b), fst.num_ilabels, alternatives=3)
+                for b in range(batch.size)]
+        flat = wf.lattices_from_lists(nets)
+        del nets
+        noff_l, aoff_l, fr_l, to_l, lab_l, w_l = (torch.as_tensor(x, device=dev) for x in flat)
+        n_nodes, n_larcs = int(flat[0][-1]), int(flat[1][-1])
+        log(f"  {n_nodes} nodes, {n_larcs} lattice arcs ({int((flat[4] < 0).sum())} epsilon), "
+            f"built in {time.time() - t:.1f} s")
+        d.set_scores(theta)
+        ms_l, prof_l = time_steps(lambda: wf.lattice_forward(d, noff_l, aoff_l, fr_l, to_l, lab_l, w_l),
+                                  args.steps, args.warmup, d)
+        _, st_l = wf.lattice_forward(d, noff_l, aoff_l, fr_l, to_l, lab_l, w_l)
+        ok_l = int((st_l == wf.STATUS_OK).sum().item())
+        k_l = kernel_table(prof_l, {"lattice": lattice_bytes(d, fst.num_states, n_nodes, flat[4])}, args.steps)
+        lattice = {"workload": f"trigram tagger WFST ({fst.num_arcs} arcs); {batch.size} confusion networks "
+                               f"around the main batch's sentences: {n_nodes} nodes, {n_larcs} arcs (token + 3 "
+                               "Zipf(1.1) competitors per slot, epsilon with probability 0.1, Dirichlet(1) "
+                               "slot weights); pass = log Z of the FST composed with every lattice",
+                   "lattice_arcs_per_s": round(n_larcs / (ms_l * 1e-3), 1),
+                   "slots_per_s": round(n_sym / (ms_l * 1e-3), 1), "ms_per_pass": round(ms_l, 4),
+                   "lattices_ok": ok_l, "roofline": roofline_of(k_l), "kernels": k_l}
+        del noff_l, aoff_l, fr_l, to_l, lab_l, w_l, flat
 
     bigram = None
     if "bigram" in want:
@@ -554,6 +593,7 @@ def main():
         "batched_viterbi_symbols_per_s": round(n_sym / (kernels["viterbi"]["ms_per_pass"] * 1e-3), 1),
         "per_sentence": per_sentence,
         "training_1024": training,
+        "lattice_4096": lattice,
         "bigram_16384": bigram,
         "powerlaw_1m": powerlaw,
         "cpu_oracle_threads": cpu_mt,

@@ -388,11 +388,12 @@ def confusion_network(seed: int, tokens, num_ilabels: int, alternatives: int = 3
     an epsilon arc; the slot's weights are the logs of a Dirichlet(1) draw.
     Returns (num_nodes, arcs)."""
     rng = np.random.default_rng(seed)
+    tokens = np.asarray(tokens)
+    alt = zipf_tokens(rng, num_ilabels, zipf_s, alternatives * tokens.size).reshape(tokens.size, alternatives)
+    dele = rng.random(tokens.size) < deletion
     arcs = []
-    for t, w in enumerate(np.asarray(tokens)):
-        labels = [int(w)] + [int(x) for x in zipf_tokens(rng, num_ilabels, zipf_s, alternatives)]
-        if rng.random() < deletion:
-            labels.append(-1)
+    for t, w in enumerate(tokens):
+        labels = [int(w)] + [int(x) for x in alt[t]] + ([-1] if dele[t] else [])
         p = rng.dirichlet(np.ones(len(labels)))
         arcs += [(t, t + 1, a, float(np.log(max(pi, 1e-30)))) for a, pi in zip(labels, p)]
-    return len(tokens) + 1, arcs
+    return tokens.size + 1, arcs
