@@ -729,6 +729,53 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 constexpr int kSliceCache = 32;  // slice headers of the step's label staged in LDS
 
 constexpr int rev_key_prefetch(int nt) { return nt >= 1024 ? 3 : nt >= 512 ? 5 : 9; }
+// What a backward step needs besides its keys, staged in LDS for kBwdWin
+// steps at a time (a ring indexed by step): the loads of a step's keys and
+// alpha values then wait on no other global load.
+constexpr int kBwdWin = 8;
+// Reserve `mine` consecutive slots per lane at an LDS counter with one atomic
+// per wavefront: returns the lane's first slot.  Called by the lanes active at
+// that point (inactive lanes take no slots); the lowest active lane does the
+// atomic.  mine < 16.
+__device__ __forceinline__ int wave_append(int mine, int *counter, int lane)
+{
+    int pre = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {  // exclusive prefix of mine over the lower lanes, bit by bit
+        const uint64_t m = __ballot((mine >> k) & 1);
+        pre += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << k;
+        total += __popcll(m) << k;
+    }
+    const int leader = __builtin_ctzll(__ballot(1));
+    int base = 0;
+    if (lane == leader && total > 0) base = atomicAdd(counter, total);
+    return __shfl(base, leader, 64) + pre;
+}
+static_assert(sizeof(SliceInfo) == sizeof(int4), "slice headers move as int4");
+typedef int v4i __attribute__((ext_vector_type(4)));
+struct BwdStep {
+    int32_t slice_first, n_slices, seg_first, n_segs, n_multi, n_slots;  // reverse label of w_t
+    int32_t f_seg_first, f_n_segs;  // forward label of w_{t-1} (none at t = 1)
+    const float *ap;                // alpha~ of token i-1 (with records)
+    float *bp;                      // beta tape slot of token i
+    double aC;                      // log scale of alpha_{t-1}
+    float cm;                       // c_{t-1}
+    int32_t pad;
+};
+__device__ __forceinline__ int32_t uniform_i(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// A pointer read from memory is generic to the compiler, and generic (flat)
+// accesses also count against the LDS wait counter, so every LDS wait would
+// wait for them too; the tape pointers below are global memory.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ gfloat *to_global(float *p) { return (gfloat *)p; }
+__device__ __forceinline__ const gfloat *to_global(const float *p) { return (const gfloat *)p; }
+template <class T>
+__device__ __forceinline__ T *uniform_p(T *p)
+{
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
 constexpr int kTapeKeyPrefetch = 2;
 // Expected-count records: a step's records are staged in LDS, then copied to a
 // chunk of the record array the workgroup owns; chunks come from one global
@@ -736,7 +783,53 @@ constexpr int kTapeKeyPrefetch = 2;
 // skipped when summing).
 constexpr int kRecStage = 64;
 constexpr int kRecChunk = 256;
+static_assert(kRecStage <= kRecChunk, "one step's staged records fit a chunk");
 constexpr uint64_t kRecSentinel = ~0ull;
+
+// The step table of a backward launch: entry i describes the step of token i
+// (step t = i - o0 + 1 of its sentence).  Built in parallel over the tokens
+// just before the sweep, after the forward pass wrote the alpha scales; in a
+// checkpointed pass only the launch's block is filled (its tape slots).
+__global__ void bwd_step_table(DevLayout fl, DevLayout rl, BatchView bv, TapeView tp, BlockView bk, int32_t rec,
+                               BwdStep *__restrict__ out)
+{
+    for (int b = blockIdx.x; b < bv.B; b += gridDim.x) {
+        if (bv.status[b] != WFST_STATUS_OK) continue;  // offsets and tokens checked by the forward pass
+        const int o0 = bv.offsets[b], T = bv.offsets[b + 1] - o0;
+        int lo = 0, hi = T;
+        if (bk.c > 0) {
+            lo = bk.k * bk.c;
+            hi = min(T, lo + bk.c);
+        }
+        for (int ts = lo + 1 + (int)threadIdx.x; ts <= hi; ts += blockDim.x) {
+            const int is = o0 + ts - 1;
+            const LabelInfo r = rl.label[bv.tokens[is]];
+            BwdStep e;
+            e.slice_first = r.slice_first;
+            e.n_slices = r.n_slices;
+            e.seg_first = r.seg_first;
+            e.n_segs = r.n_segs;
+            e.n_multi = r.n_multi;
+            e.n_slots = r.n_slots;
+            e.f_seg_first = e.f_n_segs = e.pad = 0;
+            e.ap = nullptr;
+            e.bp = beta_slot(tp, bk, bv, b, o0, is);
+            e.aC = 0.0;
+            e.cm = 0.0f;
+            if (ts >= 2) {
+                const LabelInfo f = fl.label[bv.tokens[is - 1]];
+                e.f_seg_first = f.seg_first;
+                e.f_n_segs = f.n_segs;
+                if (rec) {
+                    e.ap = alpha_slot(tp, bk, bv, b, o0, is - 1);
+                    e.cm = tp.a_max[is - 1];
+                    e.aC = tp.a_log[is - 1];
+                }
+            }
+            out[is] = e;
+        }
+    }
+}
 
 // Copy the records placed at the end of the previous step (and sentinels into
 // a chunk tail left behind) from the LDS stage to the record array.
@@ -758,18 +851,19 @@ __device__ __forceinline__ void copy_staged_records(const RecordSink &rs, const 
 }
 
 template <int NT, bool GMEM>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, GMEM ? 1 : 4)  // on chip: at most 128 VGPRs, four wavefronts per SIMD
 backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                const float *__restrict__ final_score, const float *__restrict__ final_max,
                BatchView bv, TapeView tp, BlockView bk, int32_t list_cap, RecordSink rs,
-               unsigned char *__restrict__ gscratch, int64_t slot_bytes)
+               const BwdStep *__restrict__ steps, unsigned char *__restrict__ gscratch, int64_t slot_bytes)
 {
     constexpr int RPF = rev_key_prefetch(NT);
     constexpr int TPF = kTapeKeyPrefetch;
     constexpr int RB = 4;
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *smem = state_base<GMEM>(lds, gscratch, slot_bytes);
-    __shared__ SliceInfo scache[kSliceCache];                          // slice headers of the step's label
+    __shared__ __align__(16) SliceInfo scache[kSliceCache];            // slice headers of the step's label
+    __shared__ BwdStep s_win[kBwdWin];                                 // step metadata ring
     float *val0 = reinterpret_cast<float *>(smem);                     // [Q+1]
     float *val1 = val0 + (Q + 1);                                      // [Q+1]
     int32_t *mark = reinterpret_cast<int32_t *>(val1 + (Q + 1));       // [Q+1] step stamp of states to compute
@@ -786,6 +880,9 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const float fmax0 = *final_max;
+    // raw buffer view of the reverse slice headers (word 3: 32-bit data format, the gfx9 encoding)
+    const __amdgpu_buffer_rsrc_t slice_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)rl.slice, (short)0, (int)min<int64_t>(rl.n_slice * (int64_t)sizeof(SliceInfo), INT32_MAX), 0x00020000);
     const double fx = rs.acc ? *rs.fx_scale : 0.0;  // fixed-point scale of the accumulators
     if (tid == 0) {
         s_rn = 0;
@@ -832,7 +929,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         if (t1 == T) {
             // beta^_T on the destinations of w_T, for the expected counts
             const LabelInfo lf = fl.label[bv.tokens[o1 - 1]];
-            float *tape = beta_slot(tp, bk, bv, b, o0, o1 - 1);
+            gfloat *tape = to_global(beta_slot(tp, bk, bv, b, o0, o1 - 1));
             for (int j = tid; j < lf.n_segs; j += NT) tape[j] = vT[fl.seg_key[lf.seg_first + j]];
             if (tid == 0) {
                 tp.b_max[o1 - 1] = 0.0f;
@@ -842,7 +939,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         } else {  // resume from beta^_{t1} kept by the previous (later) block
             const int i1 = o0 + t1 - 1;
             const LabelInfo lf = fl.label[bv.tokens[i1]];
-            const float *tape = beta_slot(tp, bk, bv, b, o0, i1);
+            const gfloat *tape = to_global(beta_slot(tp, bk, bv, b, o0, i1));
             for (int j = tid; j < lf.n_segs; j += NT) vT[fl.seg_key[lf.seg_first + j]] = tape[j];
             C = tp.b_log[i1];
         }
@@ -852,46 +949,55 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         const float gb = rs.grad_log_z ? rs.grad_log_z[b] : 1.0f;
         const double lz = tp.log_z[b];
 
-        // labels and keys of step t1, then loaded one step ahead
-        LabelInfo li = rl.label[bv.tokens[o0 + t1 - 1]];  // reverse label of w_t
-        int rk[RPF];                                       // its segment keys (source states)
+        // metadata of steps t1, t1-1, ... staged in LDS; keys, alpha values
+        // and slice headers of a step loaded one step ahead
+        auto fill_window = [&](int thi) {  // entries of steps thi, thi-1, ... (one load each)
+            if (tid < kBwdWin && thi - tid > t0) s_win[(thi - tid) & (kBwdWin - 1)] = steps[o0 + thi - tid - 1];
+        };
+        fill_window(t1);
+        int w_lo = max(t0 + 1, t1 - kBwdWin + 1);  // lowest step in the ring
+        __syncthreads();
+        LabelInfo li{};  // reverse label of w_t
+        int lf_first, lf_n;   // forward label of w_{t-1}: the states to compute
+        const gfloat *ap;     // alpha~_{t-1} (records)
+        gfloat *bp;           // beta tape slot of token i
+        float cm;             // c_{t-1}
+        double aC;            // log scale of alpha_{t-1}
+        {
+            const BwdStep &e = s_win[t1 & (kBwdWin - 1)];
+            li.slice_first = uniform_i(e.slice_first);
+            li.n_slices = uniform_i(e.n_slices);
+            li.seg_first = uniform_i(e.seg_first);
+            li.n_segs = uniform_i(e.n_segs);
+            li.n_multi = uniform_i(e.n_multi);
+            li.n_slots = uniform_i(e.n_slots);
+            lf_first = uniform_i(e.f_seg_first);
+            lf_n = uniform_i(e.f_n_segs);
+            ap = to_global(uniform_p(e.ap));
+            bp = to_global(uniform_p(e.bp));
+            cm = e.cm;
+            aC = e.aC;
+        }
+        int rk[RPF];  // segment keys of li (source states)
+        int tk[TPF];  // keys of lf
+        float ta[TPF];  // alpha~_{t-1} on them (records only; normaliser cm subtracted at use)
+        int4 sl = make_int4(0, 0, 0, 0);  // slice header tid of li (a SliceInfo)
 #pragma unroll
         for (int u = 0; u < RPF; ++u) {
             const int j = tid + u * NT;
             rk[u] = j < li.n_segs ? rl.seg_key[li.seg_first + j] : -1;
         }
-        LabelInfo lf{};  // forward label of w_{t-1}: the states to compute
-        int tk[TPF];
-        float ta[TPF];   // alpha~_{t-1} on them (records only; normaliser cm subtracted at use)
-        float cm = 0.0f; // c_{t-1}
-        double aC = 0.0; // log scale of alpha_{t-1}
 #pragma unroll
         for (int u = 0; u < TPF; ++u) {
-            tk[u] = -1;
-            ta[u] = WFST_NINF;
+            const int j = tid + u * NT;
+            tk[u] = j < lf_n ? fl.seg_key[lf_first + j] : -1;
+            ta[u] = rec && j < lf_n ? ap[j] : WFST_NINF;
         }
-        if (t1 >= 2) {
-            const int ip = o0 + t1 - 2;
-            lf = fl.label[bv.tokens[ip]];
-            const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
-            if (rec) {
-                cm = tp.a_max[ip];
-                aC = tp.a_log[ip];
-            }
-#pragma unroll
-            for (int u = 0; u < TPF; ++u) {
-                const int j = tid + u * NT;
-                if (j < lf.n_segs) {
-                    tk[u] = fl.seg_key[lf.seg_first + j];
-                    if (rec) ta[u] = ap[j];
-                }
-            }
-        }
-        LabelInfo lf_prev{};  // forward label of w_t: support of beta~_t, reset after the step
+        if (tid < min(li.n_slices, kSliceCache)) sl = reinterpret_cast<const int4 *>(rl.slice)[li.slice_first + tid];
+        int lfp_first = 0, lfp_n = 0;  // forward label of w_t: support of beta~_t, reset after the step
         int tk_prev[TPF];
 #pragma unroll
         for (int u = 0; u < TPF; ++u) tk_prev[u] = -1;
-        __syncthreads();
 
         for (int t = t1; t > t0; --t) {
             float *prev = (t & 1) ? val1 : val0;  // beta~_t
@@ -906,38 +1012,51 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                         mark[tk[u]] = t;
                         aval[tk[u]] = ta[u] - cm;
                     }
-                if (lf.n_segs > TPF * NT) {
-                    const int ip = i - 1;
-                    const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
-                    for (int j = tid + TPF * NT; j < lf.n_segs; j += NT) {
-                        const int q = fl.seg_key[lf.seg_first + j];
-                        mark[q] = t;
-                        aval[q] = rec ? ap[j] - cm : WFST_NINF;
-                    }
+                for (int j = tid + TPF * NT; j < lf_n; j += NT) {
+                    const int q = fl.seg_key[lf_first + j];
+                    mark[q] = t;
+                    aval[q] = rec ? ap[j] - cm : WFST_NINF;
                 }
             } else if (tid == 0) {
                 mark[start] = t;
                 aval[start] = 0.0f;  // alpha~_0 = 0 at the start state, no normaliser
             }
             const float o = rec ? (float)((t >= 2 ? aC : 0.0) + C - lz) : 0.0f;  // C = log scale of beta_t
-            for (int s = tid; s < min(li.n_slices, kSliceCache); s += NT) scache[s] = rl.slice[li.slice_first + s];
+            if (tid < min(li.n_slices, kSliceCache)) reinterpret_cast<int4 *>(scache)[tid] = sl;
             if (tid == 0) s_count = 0;
             __syncthreads();
+            // B, first half: which reverse segments of w_t have a marked source
+            // (before the next step's loads are issued: waiting for rk must not
+            // wait for them)
+            uint32_t hits = 0;
+#pragma unroll
+            for (int u = 0; u < RPF; ++u)
+                if (rk[u] >= 0 && mark[rk[u]] == t) hits |= 1u << u;
             if (stage) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
             if (t < t1) {  // tape of beta^_t (this step's input), normalised at the end of step t+1
-                float *tape = beta_slot(tp, bk, bv, b, o0, i);
 #pragma unroll
                 for (int u = 0; u < TPF; ++u)
-                    if (tk_prev[u] >= 0) tape[tid + u * NT] = prev[tk_prev[u]];
-                for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
-                    tape[j] = prev[fl.seg_key[lf_prev.seg_first + j]];
+                    if (tk_prev[u] >= 0) bp[tid + u * NT] = prev[tk_prev[u]];
+                for (int j = tid + TPF * NT; j < lfp_n; j += NT) bp[j] = prev[fl.seg_key[lfp_first + j]];
             }
-            // next step's labels and keys, in flight during this step
-            LabelInfo li_n{}, lf_n{};
-            int rk_n[RPF], tk_n[TPF];
-            float ta_n[TPF];
+            // next step's metadata from the ring (refilled every kBwdWin steps;
+            // every thread read the entries it replaces before this step's
+            // barrier), its keys, alpha values and slice headers in flight
+            // during this step
+            if (t - 1 > t0 && t - 1 < w_lo) {
+                fill_window(t - 1);
+                w_lo = max(t0 + 1, t - kBwdWin);
+                __syncthreads();
+            }
+            LabelInfo li_n{};
+            int lf_first_n = 0, lf_n_n = 0;
+            const gfloat *ap_n = nullptr;
+            gfloat *bp_n = nullptr;
             float cm_n = 0.0f;
             double aC_n = 0.0;
+            int rk_n[RPF], tk_n[TPF];
+            float ta_n[TPF];
+            int4 sl_n = make_int4(0, 0, 0, 0);
 #pragma unroll
             for (int u = 0; u < RPF; ++u) rk_n[u] = -1;
 #pragma unroll
@@ -946,37 +1065,48 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 ta_n[u] = WFST_NINF;
             }
             if (t - 1 > t0) {
-                li_n = rl.label[bv.tokens[i - 1]];
+                const BwdStep &e = s_win[(t - 1) & (kBwdWin - 1)];
+                li_n.slice_first = uniform_i(e.slice_first);
+                li_n.n_slices = uniform_i(e.n_slices);
+                li_n.seg_first = uniform_i(e.seg_first);
+                li_n.n_segs = uniform_i(e.n_segs);
+                li_n.n_multi = uniform_i(e.n_multi);
+                li_n.n_slots = uniform_i(e.n_slots);
+                lf_first_n = uniform_i(e.f_seg_first);
+                lf_n_n = uniform_i(e.f_n_segs);
+                ap_n = to_global(uniform_p(e.ap));
+                bp_n = to_global(uniform_p(e.bp));
+                cm_n = e.cm;
+                aC_n = e.aC;
 #pragma unroll
                 for (int u = 0; u < RPF; ++u) {
                     const int j = tid + u * NT;
                     if (j < li_n.n_segs) rk_n[u] = rl.seg_key[li_n.seg_first + j];
                 }
-                if (t - 1 >= 2) {
-                    const int ip = i - 2;
-                    lf_n = fl.label[bv.tokens[ip]];
-                    const float *ap = rec ? alpha_slot(tp, bk, bv, b, o0, ip) : nullptr;
-                    if (rec) {
-                        cm_n = tp.a_max[ip];
-                        aC_n = tp.a_log[ip];
-                    }
 #pragma unroll
-                    for (int u = 0; u < TPF; ++u) {
-                        const int j = tid + u * NT;
-                        if (j < lf_n.n_segs) {
-                            tk_n[u] = fl.seg_key[lf_n.seg_first + j];
-                            if (rec) ta_n[u] = ap[j];
-                        }
+                for (int u = 0; u < TPF; ++u) {
+                    const int j = tid + u * NT;
+                    if (j < lf_n_n) {
+                        tk_n[u] = fl.seg_key[lf_first_n + j];
+                        if (rec) ta_n[u] = ap_n[j];
                     }
                 }
+                if (tid < min(li_n.n_slices, kSliceCache))
+                    sl_n = reinterpret_cast<const int4 *>(rl.slice)[li_n.slice_first + tid];
             }
-            // B: reverse segments of w_t whose source is marked
+            // B, second half: the marked segments compacted with one LDS atomic
+            // per wavefront (list order does not matter: each entry is reduced
+            // on its own)
+            {
+                const int mine = __popc(hits);
+                const int pos0 = wave_append(mine, &s_count, lane);
+                int pos = pos0;
 #pragma unroll
-            for (int u = 0; u < RPF; ++u) {
-                if (rk[u] >= 0 && mark[rk[u]] == t) {
-                    const int pos = atomicAdd(&s_count, 1);
-                    if (pos < list_cap) list[pos] = make_int2(tid + u * NT, rk[u]);
-                }
+                for (int u = 0; u < RPF; ++u)
+                    if (hits >> u & 1u) {
+                        if (pos < list_cap) list[pos] = make_int2(tid + u * NT, rk[u]);
+                        ++pos;
+                    }
             }
             for (int j = tid + RPF * NT; j < li.n_segs; j += NT) {
                 const int key = rl.seg_key[li.seg_first + j];
@@ -1009,14 +1139,24 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                 LseD acc{-__builtin_huge_val(), 0.0f};
                 for (int c = c0; c < c0 + nc; ++c) {
                     const int s = c >> 6, l = c & 63;
-                    const SliceInfo si = s < kSliceCache ? scache[s] : rl.slice[li.slice_first + s];
+                    // the slice header: from the LDS cache, else by a buffer load (a plain
+                    // global load here would be merged with the LDS read into a generic one)
+                    v4i sv;
+                    if (s < kSliceCache)
+                        sv = reinterpret_cast<const v4i *>(scache)[s];
+                    else
+                        sv = __builtin_amdgcn_raw_buffer_load_b128(slice_rsrc, (li.slice_first + s) * (int)sizeof(SliceInfo),
+                                                                  0, 0);
+                    const SliceInfo si{sv.x, sv.y, sv.z, sv.w};
                     for (int r0 = 0; r0 < si.height; r0 += RB) {
                         Elem e[RB];
+                        int32_t arc_of[RB];  // arc ids, for the posteriors (loaded with the rows)
 #pragma unroll
                         for (int u = 0; u < RB; ++u) {  // no branches: all RB loads in flight together
                             const int pos = si.base + min(r0 + u, si.height - 1) * si.width + l;
                             const int32_t o = rl.other[pos];
                             const float sc = rl.score[pos];
+                            arc_of[u] = a != WFST_NINF ? rl.elem_arc[pos] : -1;
                             e[u] = r0 + u < si.height ? Elem{o, sc} : Elem{Q, 0.0f};
                         }
                         float g[RB];
@@ -1037,15 +1177,15 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
 #pragma unroll
                                 for (int u = 0; u < RB; ++u) {
                                     if (v[u] == 0.0f) continue;
-                                    const int arc = rl.elem_arc[si.base + (r0 + u) * si.width + l];
+                                    const int arc = arc_of[u];
                                     atomicAdd(&rs.acc[arc], (unsigned long long)__double2ll_rn((double)v[u] * fx));
                                 }
                             } else if (nrec > 0) {
-                                int at = atomicAdd(&s_rn, nrec);
+                                int at = wave_append(nrec, &s_rn, lane);
 #pragma unroll
                                 for (int u = 0; u < RB; ++u) {
                                     if (v[u] == 0.0f) continue;
-                                    const int arc = rl.elem_arc[si.base + (r0 + u) * si.width + l];
+                                    const int arc = arc_of[u];
                                     const uint64_t key = ((uint64_t)(uint32_t)arc << 32) | (uint32_t)i;
                                     if (at < kRecStage) {
                                         s_rkey[at] = key;
@@ -1089,8 +1229,8 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     if (s_cused + n > s_csize) {  // new chunk; the old one's unused tail gets sentinels
                         s_tailb = s_cbase + s_cused;
                         s_tailn = s_csize - s_cused;
-                        s_csize = max(kRecChunk, n);
-                        s_cbase = atomicAdd(rs.count, (unsigned long long)s_csize);
+                        s_cbase = atomicAdd(rs.count, (unsigned long long)kRecChunk);
+                        s_csize = kRecChunk;
                         s_cused = 0;
                     }
                     s_fbase = s_cbase + s_cused;
@@ -1107,20 +1247,24 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
 #pragma unroll
                 for (int u = 0; u < TPF; ++u)
                     if (tk_prev[u] >= 0) prev[tk_prev[u]] = WFST_NINF;
-                for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT)
-                    prev[fl.seg_key[lf_prev.seg_first + j]] = WFST_NINF;
+                for (int j = tid + TPF * NT; j < lfp_n; j += NT) prev[fl.seg_key[lfp_first + j]] = WFST_NINF;
             }
             if (t >= 2 && tid == 0) {
                 tp.b_max[i - 1] = 0.0f;  // the tape is normalised
                 tp.b_log[i - 1] = C;
             }
-            lf_prev = lf;
+            lfp_first = lf_first;
+            lfp_n = lf_n;
 #pragma unroll
             for (int u = 0; u < TPF; ++u) tk_prev[u] = tk[u];
             li = li_n;
-            lf = lf_n;
+            lf_first = lf_first_n;
+            lf_n = lf_n_n;
+            ap = ap_n;
+            bp = bp_n;
             aC = aC_n;
             cm = cm_n;
+            sl = sl_n;
 #pragma unroll
             for (int u = 0; u < RPF; ++u) rk[u] = rk_n[u];
 #pragma unroll
@@ -1132,11 +1276,11 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         __syncthreads();
         if (t0 >= 1) {  // tape of beta^_{t0}, the last step's output (a block boundary)
             float *fin = ((t0 + 1) & 1) ? val0 : val1;
-            float *tape = beta_slot(tp, bk, bv, b, o0, o0 + t0 - 1);
+            gfloat *tape = to_global(beta_slot(tp, bk, bv, b, o0, o0 + t0 - 1));
 #pragma unroll
             for (int u = 0; u < TPF; ++u)
                 if (tk_prev[u] >= 0) tape[tid + u * NT] = fin[tk_prev[u]];
-            for (int j = tid + TPF * NT; j < lf_prev.n_segs; j += NT) tape[j] = fin[fl.seg_key[lf_prev.seg_first + j]];
+            for (int j = tid + TPF * NT; j < lfp_n; j += NT) tape[j] = fin[fl.seg_key[lfp_first + j]];
         }
         __syncthreads();
     }
@@ -1252,7 +1396,7 @@ __device__ __forceinline__ void fetch_visit(const DevLayout &fl, const TapeView 
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) x.key[u] = -1;
     if (!vi.live) return;
-    const float *tb = vi.b_ptr;
+    const gfloat *tb = to_global(vi.b_ptr);
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
         const int j = tid + u * NT;
@@ -1266,7 +1410,7 @@ __device__ __forceinline__ void fetch_visit(const DevLayout &fl, const TapeView 
         return;
     }
     const LabelInfo lp = fl.label[vi.prev_label];
-    const float *ta = vi.a_ptr;
+    const gfloat *ta = to_global(vi.a_ptr);
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
         const int j = tid + u * NT;
@@ -1413,11 +1557,11 @@ counts_kernel(DevLayout fl, DevLayout rl, int32_t Q, int32_t start, BatchView bv
                     }
                     // rare: more entries than NT * kPrefetch
                     for (int j = tid + kPrefetch * NT; j < lf.n_segs; j += NT)
-                        bd[j] = (vi.b_ptr[j] - vi.bm) + vi.o;
+                        bd[j] = (to_global(vi.b_ptr)[j] - vi.bm) + vi.o;
                     if (vi.prev_label >= 0) {
                         const LabelInfo lp = fl.label[vi.prev_label];
                         for (int j = tid + kPrefetch * NT; j < lp.n_segs; j += NT)
-                            den[fl.seg_key[lp.seg_first + j]] = CEnt{vi.a_ptr[j] - vi.cm, v};
+                            den[fl.seg_key[lp.seg_first + j]] = CEnt{to_global(vi.a_ptr)[j] - vi.cm, v};
                     }
                 }
                 const VisitInfo cur = vi;
@@ -1886,9 +2030,10 @@ constexpr int kScoreStage = 10112;  // floats (39.5 KiB of LDS: four workgroups 
 
 constexpr int kScoreUnroll = 8;  // elements per thread in flight
 
+template <bool STAGED>  // scores from the LDS stage, else from global memory (kept apart: no generic loads)
 __device__ __forceinline__ void scatter_label_layout(const LabelInfo &li, float *__restrict__ out,
                                                      const int32_t *__restrict__ elem_arc, const float *stage,
-                                                     int32_t lo, bool staged, const float *__restrict__ score)
+                                                     int32_t lo, const float *__restrict__ score)
 {
     const int32_t *ea = elem_arc + li.elem_first;
     float *o = out + li.elem_first;
@@ -1903,7 +2048,7 @@ __device__ __forceinline__ void scatter_label_layout(const LabelInfo &li, float 
 #pragma unroll
         for (int u = 0; u < kScoreUnroll; ++u) {
             v[u] = 0.0f;  // padding keeps score 0
-            if (arc[u] >= 0) v[u] = staged ? stage[arc[u] - lo] : score[arc[u]];
+            if (arc[u] >= 0) v[u] = STAGED ? stage[arc[u] - lo] : score[arc[u]];
         }
 #pragma unroll
         for (int u = 0; u < kScoreUnroll; ++u) {
@@ -1941,8 +2086,13 @@ scatter_scores_by_label(const LabelInfo *__restrict__ fl, const LabelInfo *__res
         }
     }
     __syncthreads();
-    scatter_label_layout(fl[a], out_f, arc_f, stage, r.x, staged, score);
-    scatter_label_layout(rl[a], out_r, arc_r, stage, r.x, staged, score);
+    if (staged) {
+        scatter_label_layout<true>(fl[a], out_f, arc_f, stage, r.x, score);
+        scatter_label_layout<true>(rl[a], out_r, arc_r, stage, r.x, score);
+    } else {
+        scatter_label_layout<false>(fl[a], out_f, arc_f, stage, r.x, score);
+        scatter_label_layout<false>(rl[a], out_r, arc_r, stage, r.x, score);
+    }
 }
 
 // Scale of the fixed-point count accumulators: 2^S with S the largest integer

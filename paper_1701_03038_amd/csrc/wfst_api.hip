@@ -96,7 +96,7 @@ enum WsSlot {
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
     W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_SCAN0,
-    W_SCAN1, W_LATNODE, W_LATSCALE, W_NUM
+    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
@@ -585,15 +585,19 @@ int launch_backward(const wfst_fst *fc, hipStream_t s, const BatchView &bv, cons
     TRY(sweep_shape(f, s, backward_sweep<NT, false>, backward_sweep<NT, true>, NT, bytes, bytes, false, bv.B, sh));
     if (sh.gmem && rs.key)
         return set_err(WFST_EUNSUPPORTED, "count records need the on-chip backward sweep");
+    BwdStep *steps = nullptr;
+    TRY(ensure_t(f->ws[W_BSTEP], std::max<int64_t>(bv.N, 1), s, &steps));
     ProfScope prof(f, s, WFST_KERNEL_BACKWARD);
+    hipLaunchKernelGGL(bwd_step_table, dim3(grid_for(bv.B, 1)), dim3(64), 0, s, f->fwd, f->rev, bv, tp, bk,
+                       (int32_t)(rs.key != nullptr || rs.acc != nullptr), steps);
     if (sh.gmem)
         hipLaunchKernelGGL((backward_sweep<NT, true>), dim3(sh.grid), dim3(NT), 0, s, f->fwd, f->rev, f->Q,
                            f->start, (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
-                           backward_list_cap(f), rs, sh.scratch, sh.slot);
+                           backward_list_cap(f), rs, (const BwdStep *)steps, sh.scratch, sh.slot);
     else
         hipLaunchKernelGGL((backward_sweep<NT, false>), dim3(sh.grid), dim3(NT), sh.lds, s, f->fwd, f->rev, f->Q,
                            f->start, (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
-                           backward_list_cap(f), rs, nullptr, (int64_t)0);
+                           backward_list_cap(f), rs, (const BwdStep *)steps, nullptr, (int64_t)0);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -1614,9 +1618,9 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
                 return reduce_records(f, s, (int64_t)got[0], N, rs.key, rs.val, k1, v1, grad_arc_score);
             }
             // slots overflowed: grow to a bound no schedule can pass and run again.  A
-            // chunk holds max(kRecChunk, one step's records <= kRecStage) slots and
-            // is left with a tail under kRecStage; there are at most
-            // records / kRecChunk chunks plus one per workgroup and launch.
+            // chunk holds kRecChunk slots and is left with a tail under kRecStage;
+            // there are at most records / kRecChunk chunks plus one per workgroup
+            // and launch.
             const int64_t launches = bk.c > 0 ? K : 1;
             cap = 3 * (int64_t)got[1] + (int64_t)kRecStage * B * launches + 4096;
             f->rec_cap = std::max<int64_t>(f->rec_cap, std::min(kRecordsMax, (int64_t)got[0] + (int64_t)got[0] / 4));
