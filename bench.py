@@ -433,7 +433,8 @@ def main():
                                   args.steps, args.warmup, d)
         _, st_l = wf.lattice_forward(d, noff_l, aoff_l, fr_l, to_l, lab_l, w_l)
         ok_l = int((st_l == wf.STATUS_OK).sum().item())
-        k_l = kernel_table(prof_l, {"lattice": lattice_bytes(d, fst.num_states, n_nodes, flat[4])}, args.steps)
+        k_l = kernel_table(prof_l, {"lattice": lattice_bytes(d, fst.num_states, n_nodes, flat[4])}, args.steps,
+                           traffic)
         lattice = {"workload": f"trigram tagger WFST ({fst.num_arcs} arcs); {batch.size} confusion networks "
                                f"around the main batch's sentences: {n_nodes} nodes, {n_larcs} arcs (token + 3 "
                                "Zipf(1.1) competitors per slot, epsilon with probability 0.1, Dirichlet(1) "
@@ -533,7 +534,7 @@ def main():
             lz.sum().backward()
         ms5, prof5 = time_steps(train5, args.powerlaw_steps, 1, d5)
         k5 = kernel_table(prof5, algorithmic_bytes(d5, b5, Q=f5.num_states), args.powerlaw_steps,
-                          fused_counts=True)
+                          load_traffic("traffic_powerlaw_1m.json"), fused_counts=True)
         n5 = int(b5.offsets[-1])
         total5 = step_bytes(k5, args.powerlaw_steps)
         powerlaw = {"workload": f"power-law WFST: {f5.num_states} states, {f5.num_arcs} arcs, out-degree "
