@@ -69,8 +69,16 @@ typedef struct wfst_options {
     int32_t threads_per_sentence; /* workgroup size per sentence (64,128,256,512,1024); 0 = auto */
     int32_t checkpoint;         /* forward tape: -1/0 = auto, 1 = force sqrt(T) checkpointing, 2 = never */
     int32_t state_memory;       /* per-sentence state vectors of the sweeps: 0 = auto (LDS when they fit,
-                                   else a slot of global memory per workgroup), 1 = LDS only (larger FSTs
-                                   are refused), 2 = always global memory */
+                                   else global memory: the forward sweep then runs as a team sweep, below,
+                                   the other sweeps with a slot of global memory per workgroup),
+                                   1 = LDS only (larger FSTs are refused), 2 = always global memory, one
+                                   slot per workgroup, 3 = always global memory with the team forward
+                                   sweep.  Team sweep: the workgroups on one XCD form a team that runs one
+                                   sentence at a time, sharing out each step's slices and meeting at a
+                                   device-scope barrier after the step (a cooperative launch; not used
+                                   inside graphs, nor where the device cannot launch cooperatively, which
+                                   fall back to per-workgroup slots).  A barrier wait is bounded: on a
+                                   timeout the team stops and wfst_fst_health reports bit 64. */
     int64_t tape_budget_bytes;  /* auto mode checkpoints when the full tape exceeds this; 0 = 8 GiB */
     int64_t count_records;      /* expected counts: 0 = auto (per-visit records of the backward pass, sorted
                                    and summed per arc, while they fit; else the label-grouped count kernel
@@ -167,7 +175,8 @@ int wfst_fst_profile_read(wfst_fst *fst, double *ms, int64_t *launches, int32_t 
  * stops that piece of work and sets a bit instead of running away:
  *   1 queue overrun, 2 count work item out of range, 4 visit / token /
  *   sentence index out of range, 8 partial-count slot out of range,
- *   16 sort scatter out of range, 32 label grouping overflow.
+ *   16 sort scatter out of range, 32 label grouping overflow, 64 a team
+ *   sweep's barrier timed out (its results are invalid).
  * Bits are sticky across calls.  *flags (host) receives the word after the
  * FST's work queued on `stream` has finished (the call synchronises the
  * stream); clear != 0 resets the word afterwards.  0 means healthy. */

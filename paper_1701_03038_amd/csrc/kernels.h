@@ -44,6 +44,7 @@ enum HealthBit : uint32_t {
     H_SLOT = 8u,       // a split-label partial slot is beyond its buffer
     H_SCATTER = 16u,   // a sort scatter position is out of range
     H_GROUP = 32u,     // label grouping produced more items than reserved
+    H_TEAM = 64u,      // a team sweep's barrier timed out (the team stopped; results invalid)
 };
 
 // Capacities the count kernels check their device-side inputs against.

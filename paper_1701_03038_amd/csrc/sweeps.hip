@@ -41,6 +41,12 @@ __device__ __forceinline__ float unord_f32(uint32_t k)
 }
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+// A pointer read from memory is generic to the compiler, and generic (flat)
+// accesses also count against the LDS wait counter, so every LDS wait would
+// wait for them too; tape pointers read from tables are global memory.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ gfloat *to_global(float *p) { return (gfloat *)p; }
+__device__ __forceinline__ const gfloat *to_global(const float *p) { return (const gfloat *)p; }
 
 __device__ __forceinline__ float wave_max_f(float v)
 {
@@ -714,6 +720,316 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     }
 }
 
+// =====================================================================
+// Team forward sweep, for state vectors in global memory.  The workgroups of
+// a team run one sentence together: each step's slices are shared out among
+// the members, which meet at a barrier after the step.  The team's state
+// vector is then gathered by many compute units within the same step, so its
+// lines are reused from L2/MALL instead of each random gather fetching a line
+// from HBM for one value.  Same arithmetic as the forward sweep, except that
+// the stored state is alpha_t - C_{t-1} (the step max is known only after the
+// barrier) and the step's normaliser is subtracted when it is read.
+// =====================================================================
+constexpr int kTeamSpin = 1 << 24;  // polls per barrier wait before the team gives up
+
+struct TeamView {
+    int32_t G = 0;                  // workgroups per team (grid = G * n_teams)
+    int32_t n_teams = 0;
+    int64_t q1 = 0;                 // Q + 1 rounded up to 64 (vector stride)
+    float *vec = nullptr;           // [n_teams][3][q1] rotating state vectors
+    double *pmax = nullptr;         // [n_teams][2][G] members' step maxima, by step parity
+    double *pz = nullptr;           // [n_teams][G][2] members' partial log Z (max, sum)
+    double *part = nullptr;         // [n_teams][max_slots] chunk values of multi-chunk segments (rank 0)
+    unsigned int *bar = nullptr;    // [n_teams] barrier counters, zero at launch
+    int32_t *abort = nullptr;       // set when a member times out; every member then stops
+};
+
+// Team barrier number k (counted from 1): thread 0 of each member announces
+// its arrival and polls until all G members have arrived.  Device-scope
+// fences on both sides make the members' global writes visible to each other.
+// Returns false when the team has been stopped (timeout anywhere).
+__device__ __forceinline__ bool team_sync(const TeamView &tv, int team, unsigned int k, uint32_t *health)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(&tv.bar[team], 1u);
+        const unsigned int target = k * (unsigned int)tv.G;
+        int ok = 1;
+        for (int spin = 0;; ++spin) {
+            if (__hip_atomic_load(&tv.bar[team], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(tv.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if (spin >= kTeamSpin) {
+                atomicOr(health, H_TEAM);
+                atomicExch(tv.abort, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// LSE of one chunk (a lane's column of a slice), terms u[src] - cprev + score
+// in FP64 (u: the previous step's stored state), rows in layout order.
+template <int RB>
+__device__ __forceinline__ double team_chunk(const DevLayout &L, const SliceInfo &si, int lane, const float *u,
+                                             double cprev, int32_t dead)
+{
+    const int col = si.base + lane;
+    LseD acc{-__builtin_huge_val(), 0.0f};
+    for (int r0 = 0; r0 < si.height; r0 += RB) {
+        int32_t o[RB];
+        float sc[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {  // rows past the height re-read the last row, then count as dead
+            const int at = col + min(r0 + r, si.height - 1) * si.width;
+            o[r] = L.other[at];
+            sc[r] = L.score[at];
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int src = r0 + r < si.height ? o[r] : dead;
+            const float x = u[src];
+            if (x != WFST_NINF) lse_push_d(acc, ((double)x - cprev) + (double)sc[r]);
+        }
+    }
+    return lse_value_d(acc);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ final_score, BatchView bv,
+                   TapeView tp, BlockView bk, float *__restrict__ log_z_out, TeamView tv)
+{
+    constexpr int NW = NT / 64;
+    constexpr int RB = 8;
+    __shared__ unsigned long long s_cmax;
+    __shared__ double s_rm[NW];
+    __shared__ float s_rs[NW];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+    // members of a team sit on one XCD when workgroups are dealt round-robin over the 8 XCDs
+    const int team = (int)(blockIdx.x % 8u) + 8 * (int)((blockIdx.x / 8u) / (unsigned)tv.G);
+    const int rank = (int)((blockIdx.x / 8u) % (unsigned)tv.G);
+    const int G = tv.G;
+    float *vbase = tv.vec + (int64_t)team * 3 * tv.q1;
+    double *pmax = tv.pmax + (int64_t)team * 2 * G;
+    double *pz = tv.pz + (int64_t)team * 2 * G;
+    double *part = tv.part + (int64_t)team * max(fl.max_slots, 1);
+    unsigned int nbar = 0;
+    // all three vectors -inf (the invariant between sentences)
+    for (int64_t x = (int64_t)rank * NT + tid; x < 3 * tv.q1; x += (int64_t)G * NT) vbase[x] = WFST_NINF;
+    if (!team_sync(tv, team, ++nbar, bv.health)) return;
+
+    for (int item = team; item < bv.B; item += tv.n_teams) {
+        const int b = bv.order[item];
+        int o0, o1, t0 = 0, t1 = 0;
+        if (bk.c == 0) {
+            const int st = check_sentence<NT>(bv, b, o0, o1);  // the same verdict in every member
+            if (st != WFST_STATUS_OK) {
+                if (rank == 0 && tid == 0) {
+                    bv.status[b] = st;
+                    log_z_out[b] = WFST_NINF;
+                    tp.log_z[b] = -__builtin_huge_val();
+                }
+                continue;
+            }
+            t1 = o1 - o0;
+        } else {
+            if (bv.status[b] != WFST_STATUS_OK) continue;
+            o0 = bv.offsets[b];
+            o1 = bv.offsets[b + 1];
+            t0 = bk.k * bk.c;
+            t1 = min(o1 - o0, t0 + bk.c);
+            if (t1 <= t0) continue;
+        }
+        const int T = o1 - o0;
+        // initial state in vector t0 % 3 (already normalised: its step max is 0)
+        float *v0 = vbase + (int64_t)(t0 % 3) * tv.q1;
+        int lc_first = 0, lc_n = 0;  // segments of the checkpoint's label (block mode)
+        if (t0 == 0) {
+            if (rank == 0 && tid == 0) v0[start] = 0.0f;
+        } else {
+            const int ic = o0 + t0 - 1;
+            const LabelInfo lc = fl.label[bv.tokens[ic]];
+            lc_first = lc.seg_first;
+            lc_n = lc.n_segs;
+            const float *ta = tp.alpha + tp.ck_off[ic];
+            for (int j = rank * NT + tid; j < lc_n; j += G * NT) v0[fl.seg_key[lc_first + j]] = ta[j];
+        }
+        if (!team_sync(tv, team, ++nbar, bv.health)) return;
+        double C = 0.0, cprev = 0.0;
+        for (int t = t0 + 1; t <= t1; ++t) {
+            const float *prev = vbase + (int64_t)((t - 1) % 3) * tv.q1;
+            float *cur = vbase + (int64_t)(t % 3) * tv.q1;
+            float *old = vbase + (int64_t)((t + 1) % 3) * tv.q1;
+            const int i = o0 + t - 1;
+            const LabelInfo li = uniform_label(fl.label[bv.tokens[i]]);
+            // clear the support of alpha_{t-2} (read by everyone at step t-1, before the last barrier)
+            if (t - 2 == 0) {
+                if (rank == 0 && tid == 0) old[start] = WFST_NINF;
+            } else if (t - 2 >= t0) {
+                int o_first = lc_first, o_n = lc_n;
+                if (t - 2 > t0) {
+                    const LabelInfo lo = fl.label[bv.tokens[i - 2]];
+                    o_first = lo.seg_first;
+                    o_n = lo.n_segs;
+                }
+                for (int j = rank * NT + tid; j < o_n; j += G * NT) old[fl.seg_key[o_first + j]] = WFST_NINF;
+            }
+            if (tid == 0) s_cmax = 0ull;
+            __syncthreads();
+            double my_max = -__builtin_huge_val();
+            // slices holding chunks of multi-chunk segments: member 0; the rest dealt out
+            const int n_ms = (li.n_slots + 63) / 64;
+            if (rank == 0)
+                for (int s = wave; s < n_ms; s += NW) {
+                    const SliceInfo si = fl.slice[li.slice_first + s];
+                    const int c = s * 64 + lane;
+                    if (lane < si.width) {
+                        const double v = team_chunk<RB>(fl, si, lane, prev, cprev, Q);
+                        if (c < li.n_slots) {
+                            part[c] = v;
+                        } else {
+                            const int d = fl.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)];
+                            if (v != -__builtin_huge_val()) cur[d] = (float)v;
+                            my_max = fmax(my_max, v);
+                        }
+                    }
+                }
+            for (int s = n_ms + rank * NW + wave; s < li.n_slices; s += G * NW) {
+                const SliceInfo si = fl.slice[li.slice_first + s];
+                if (lane < si.width) {
+                    const int c = s * 64 + lane;
+                    const int d = fl.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)];
+                    const double v = team_chunk<RB>(fl, si, lane, prev, cprev, Q);
+                    if (v != -__builtin_huge_val()) cur[d] = (float)v;
+                    my_max = fmax(my_max, v);
+                }
+            }
+            if (rank == 0) {
+                __syncthreads();  // part[] complete (this member's own writes)
+                for (int j = tid; j < li.n_multi; j += NT) {
+                    const SegChunk sc = fl.seg_chunk[li.seg_first + j];
+                    LseD acc{-__builtin_huge_val(), 0.0f};
+                    for (int p = 0; p < sc.count; ++p) {  // chunks in order
+                        const double x = part[sc.first + p];
+                        if (x != -__builtin_huge_val()) lse_push_d(acc, x);
+                    }
+                    const double v = lse_value_d(acc);
+                    if (v != -__builtin_huge_val()) cur[fl.seg_key[li.seg_first + j]] = (float)v;
+                    my_max = fmax(my_max, v);
+                }
+            }
+            block_max_d(my_max, &s_cmax, lane);
+            __syncthreads();
+            if (tid == 0) pmax[(t & 1) * G + rank] = unord_f64(s_cmax);
+            if (!team_sync(tv, team, ++nbar, bv.health)) return;
+            // the step max over all members (same order in every member)
+            double c = -__builtin_huge_val();
+            for (int r = 0; r < G; ++r) c = fmax(c, pmax[(t & 1) * G + r]);
+            if (!(c > -__builtin_huge_val())) c = 0.0;
+            C += c;
+            // normalised tape: alpha^_t = stored - c_t on the destinations of w_t
+            float *tape;
+            if (bk.c > 0) {
+                int blk;
+                tape = ((bk.k & 1) ? bk.abuf[1] : bk.abuf[0]) + block_rel(bk, bv, b, o0, i, blk);
+            } else if (tp.ck_off) {
+                tape = tp.ck_off[i] >= 0 ? tp.alpha + tp.ck_off[i] : nullptr;
+            } else {
+                tape = tp.alpha + bv.tok_off[i];
+            }
+            if (tape)
+                for (int j = rank * NT + tid; j < li.n_segs; j += G * NT) {
+                    const float x = cur[fl.seg_key[li.seg_first + j]];
+                    to_global(tape)[j] = x == WFST_NINF ? WFST_NINF : (float)((double)x - c);
+                }
+            if (rank == 0 && tid == 0 && bk.c == 0) {
+                tp.a_max[i] = 0.0f;
+                tp.a_log[i] = C;
+            }
+            cprev = c;
+        }
+        // log Z = C_T + LSE_q(alpha^_T[q] + f[q]) (members' partial sums combined in member order)
+        if (bk.c == 0) {
+            LseD acc{-__builtin_huge_val(), 0.0f};
+            LabelInfo lf{};
+            const float *fin = vbase + (int64_t)(t1 % 3) * tv.q1;
+            if (T == 0) {
+                if (rank == 0 && tid == 0) {
+                    const float f = final_score[start];
+                    if (f != WFST_NINF) acc = LseD{(double)f, 1.0f};
+                }
+            } else {
+                lf = fl.label[bv.tokens[o1 - 1]];
+                for (int j = rank * NT + tid; j < lf.n_segs; j += G * NT) {
+                    const int d = fl.seg_key[lf.seg_first + j];
+                    const float x = fin[d], f = final_score[d];
+                    if (x == WFST_NINF || f == WFST_NINF) continue;
+                    lse_push_d(acc, ((double)x - cprev) + (double)f);
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) acc = lse_merge_d(acc, LseD{__shfl_xor(acc.m, o, 64), __shfl_xor(acc.s, o, 64)});
+            if (lane == 0) {
+                s_rm[wave] = acc.m;
+                s_rs[wave] = acc.s;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                LseD tot{s_rm[0], s_rs[0]};
+                for (int w = 1; w < NW; ++w) tot = lse_merge_d(tot, LseD{s_rm[w], s_rs[w]});
+                pz[2 * rank] = tot.m;
+                pz[2 * rank + 1] = (double)tot.s;
+            }
+            if (!team_sync(tv, team, ++nbar, bv.health)) return;
+            if (rank == 0 && tid == 0) {
+                LseD tot{pz[0], (float)pz[1]};
+                for (int r = 1; r < G; ++r) tot = lse_merge_d(tot, LseD{pz[2 * r], (float)pz[2 * r + 1]});
+                const double lzr = lse_value_d(tot);
+                if (lzr == -__builtin_huge_val()) {
+                    bv.status[b] = WFST_STATUS_NO_PATH;
+                    log_z_out[b] = WFST_NINF;
+                    tp.log_z[b] = -__builtin_huge_val();
+                } else {
+                    const double lz = C + lzr;
+                    bv.status[b] = WFST_STATUS_OK;
+                    log_z_out[b] = (float)lz;
+                    tp.log_z[b] = lz;
+                }
+            }
+        }
+        // restore the invariant: clear the supports of alpha_{t1-1} and alpha_{t1}
+        for (int back = 0; back < 2; ++back) {
+            const int tt = t1 - back;
+            if (tt < t0) break;
+            float *v = vbase + (int64_t)(tt % 3) * tv.q1;
+            if (tt == 0) {
+                if (rank == 0 && tid == 0) v[start] = WFST_NINF;
+            } else {
+                int t_first = lc_first, t_n = lc_n;
+                if (tt > t0) {
+                    const LabelInfo lt = fl.label[bv.tokens[o0 + tt - 1]];
+                    t_first = lt.seg_first;
+                    t_n = lt.n_segs;
+                }
+                for (int j = rank * NT + tid; j < t_n; j += G * NT) v[fl.seg_key[t_first + j]] = WFST_NINF;
+            }
+        }
+        if (!team_sync(tv, team, ++nbar, bv.health)) return;
+    }
+}
+
 // Backward pass (paper, Algorithm 2 second loop, with the index typos fixed):
 // beta_{t-1}[s] = LSE over the arcs k with input w_t leaving s of
 // theta_k + beta_t[dst_k].  beta_{t-1} is only ever read on the states
@@ -763,12 +1079,6 @@ struct BwdStep {
     int32_t pad;
 };
 __device__ __forceinline__ int32_t uniform_i(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-// A pointer read from memory is generic to the compiler, and generic (flat)
-// accesses also count against the LDS wait counter, so every LDS wait would
-// wait for them too; the tape pointers below are global memory.
-typedef __attribute__((address_space(1))) float gfloat;
-__device__ __forceinline__ gfloat *to_global(float *p) { return (gfloat *)p; }
-__device__ __forceinline__ const gfloat *to_global(const float *p) { return (const gfloat *)p; }
 template <class T>
 __device__ __forceinline__ T *uniform_p(T *p)
 {

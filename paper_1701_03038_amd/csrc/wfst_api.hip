@@ -96,7 +96,7 @@ enum WsSlot {
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
     W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_SCAN0,
-    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_NUM
+    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_TVEC, W_TPMAX, W_TPZ, W_TPART, W_TBAR, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
@@ -144,6 +144,7 @@ struct wfst_fst {
     int64_t bytes = 0;
     int cu_count = 0;
     size_t max_lds = 0;
+    bool coop = false;  // cooperative launches supported (team sweeps)
     std::vector<std::pair<void *, size_t>> allocs;  // owned device arrays and their bytes
     Buf ws[W_NUM];
     std::vector<TapeBufs *> tape_pool;
@@ -357,7 +358,7 @@ int sweep_shape(wfst_fst *f, hipStream_t s, KL k_lds, KG k_gmem, int nt, size_t 
                 bool need_wide, int64_t work, SweepShape &sh)
 {
     const bool fits = lds_bytes <= f->max_lds && !need_wide;
-    sh.gmem = f->state_mem == 2 || (f->state_mem == 0 && !fits);
+    sh.gmem = f->state_mem >= 2 || (f->state_mem == 0 && !fits);
     if (!sh.gmem) {
         if (!fits)
             return set_err(WFST_EUNSUPPORTED, "the FST's state vectors need " + std::to_string(lds_bytes) +
@@ -527,7 +528,7 @@ int launch_viterbi(const wfst_fst *fc, hipStream_t s, const BatchView &bv, int2 
     // on chip, segment indices are 16 bits (Q + 1 < 2^16); wider FSTs take the global form
     const bool wide = f->Q + 1 > 0xffff;
     if (no_alloc) {  // on-chip form only: its grid needs no memory beyond the caller's scratch
-        if (wide || f->state_mem == 2 || lds_viterbi(f, false) > f->max_lds)
+        if (wide || f->state_mem >= 2 || lds_viterbi(f, false) > f->max_lds)
             return set_err(WFST_EUNSUPPORTED, "the no-allocation Viterbi runs only the on-chip form "
                                               "(state vectors in LDS); this FST needs the global-memory form");
         sh.lds = lds_viterbi(f, false);
@@ -549,11 +550,58 @@ int launch_viterbi(const wfst_fst *fc, hipStream_t s, const BatchView &bv, int2 
     return WFST_OK;
 }
 
+// The team form of the forward sweep runs when its state must be in global
+// memory (auto mode) or the options ask for it, the device launches
+// cooperatively, and no graph is being captured.  One team per XCD (8 on
+// this device), each of all the workgroups that fit on that XCD's CUs.
+constexpr int kTeamsPerDevice = 8;
+
+bool team_forward_wanted(const wfst_fst *f)
+{
+    if (f->graph_mode || !f->coop) return false;
+    return f->state_mem == 3 || (f->state_mem == 0 && lds_lse(f, f->fwd) > f->max_lds);
+}
+
+template <int NT>
+int launch_team_forward(wfst_fst *f, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
+                        float *log_z)
+{
+    int per_cu = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, team_forward_sweep<NT>, NT, 0));
+    const int G = per_cu * f->cu_count / kTeamsPerDevice;
+    if (G < 1) return set_err(WFST_EUNSUPPORTED, "team sweep does not fit the device");
+    TeamView tv;
+    tv.G = G;
+    tv.n_teams = kTeamsPerDevice;
+    tv.q1 = ((int64_t)f->Q + 1 + 63) / 64 * 64;
+    unsigned int *bar = nullptr;
+    TRY(ensure_t(f->ws[W_TVEC], (int64_t)tv.n_teams * 3 * tv.q1, s, &tv.vec));
+    TRY(ensure_t(f->ws[W_TPMAX], (int64_t)tv.n_teams * 2 * G, s, &tv.pmax));
+    TRY(ensure_t(f->ws[W_TPZ], (int64_t)tv.n_teams * 2 * G, s, &tv.pz));
+    TRY(ensure_t(f->ws[W_TPART], (int64_t)tv.n_teams * std::max(f->fwd.max_slots, 1), s, &tv.part));
+    TRY(ensure_t(f->ws[W_TBAR], (int64_t)tv.n_teams + 1, s, &bar));
+    tv.bar = bar;
+    tv.abort = reinterpret_cast<int32_t *>(bar + tv.n_teams);
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t *>(bar), (int64_t)tv.n_teams + 1, 0);
+    ProfScope prof(f, s, WFST_KERNEL_FORWARD);
+    DevLayout fl = f->fwd;
+    int32_t Q = f->Q, start = f->start;
+    const float *final_score = (const float *)f->final_score;
+    BatchView bv_ = bv;
+    TapeView tp_ = tp;
+    BlockView bk_ = bk;
+    void *args[] = {&fl, &Q, &start, &final_score, &bv_, &tp_, &bk_, &log_z, &tv};
+    HIP_OK(hipLaunchCooperativeKernel((const void *)team_forward_sweep<NT>, dim3(tv.n_teams * G), dim3(NT), args, 0,
+                                      s));
+    return WFST_OK;
+}
+
 template <int NT>
 int launch_forward(const wfst_fst *fc, hipStream_t s, const BatchView &bv, const TapeView &tp, const BlockView &bk,
                    float *log_z)
 {
     wfst_fst *f = const_cast<wfst_fst *>(fc);
+    if (team_forward_wanted(f)) return launch_team_forward<NT>(f, s, bv, tp, bk, log_z);
     SweepShape sh;
     const size_t bytes = lds_lse(f, f->fwd);
     TRY(sweep_shape(f, s, forward_sweep<NT, false>, forward_sweep<NT, true>, NT, bytes, bytes, false, bv.B, sh));
@@ -572,7 +620,7 @@ int launch_forward(const wfst_fst *fc, hipStream_t s, const BatchView &bv, const
 // the fixed-point form) when the options say so or its state exceeds LDS.
 bool backward_in_gmem(const wfst_fst *f)
 {
-    return f->state_mem == 2 || (f->state_mem == 0 && lds_backward(f) > f->max_lds);
+    return f->state_mem >= 2 || (f->state_mem == 0 && lds_backward(f) > f->max_lds);
 }
 
 template <int NT>
@@ -1118,7 +1166,8 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         if (opt.checkpoint < -1 || opt.checkpoint > 2) return set_err(WFST_EINVAL, "checkpoint must be -1, 0, 1 or 2");
         if (opt.tape_budget_bytes < 0) return set_err(WFST_EINVAL, "tape_budget_bytes must be >= 0");
         if (opt.count_records < -2) return set_err(WFST_EINVAL, "count_records must be >= -2");
-        if (opt.state_memory < 0 || opt.state_memory > 2) return set_err(WFST_EINVAL, "state_memory must be 0, 1 or 2");
+        if (opt.state_memory < 0 || opt.state_memory > 3)
+            return set_err(WFST_EINVAL, "state_memory must be 0, 1, 2 or 3");
 
         hipStream_t s = as_stream(stream);
         wfst_fst *f = new wfst_fst();
@@ -1145,6 +1194,7 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
         }
         f->cu_count = prop.multiProcessorCount;
         f->max_lds = prop.sharedMemPerBlock;
+        f->coop = prop.cooperativeLaunch != 0;
         std::string err;
         int rc;
         {

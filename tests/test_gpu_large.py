@@ -1,5 +1,6 @@
 """FSTs whose per-sentence state vectors do not fit on chip: the sweeps keep
-them in a slot of global memory per workgroup, and the expected counts are
+them in a slot of global memory per workgroup (the forward sweep, in auto
+mode, as a team of workgroups per sentence), and the expected counts are
 accumulated in fixed point during the backward sweep.
 
 Forced onto small FSTs (state_memory=2) so that the oracle's brute-force-
@@ -53,6 +54,26 @@ def test_tiny_global_state(wf, chunk, nt):
         d = wf.Fst.from_synth(fst, chunk_arcs=chunk, threads_per_sentence=nt, state_memory=2)
         assert_viterbi_parity(fst, batch, d, f"gmem seed={seed}")
         assert_fb_parity(fst, batch, d, f"gmem seed={seed}")
+
+
+@pytest.mark.parametrize("chunk,nt,ck", [(16, 256, 0), (2, 64, 1), (5, 128, 1), (16, 1024, 0)])
+def test_tiny_team_forward(wf, chunk, nt, ck):
+    """The team form of the forward sweep (state_memory=3: the workgroups on
+    one XCD share each step and meet at a barrier), plain and checkpointed
+    (its block recompute runs as a team too); the other sweeps in global
+    memory per workgroup.  Includes empty, one-token and bad-token sentences."""
+    for seed in range(340, 348):
+        say(f"case: tiny team forward seed={seed} chunk={chunk} nt={nt} ck={ck}")
+        fst = synth.tiny_random_fst(seed, 2 + seed % 6, 1 + seed % 3, 6 + 2 * (seed % 13), final_prob=0.8)
+        lens = np.random.default_rng(seed).integers(0, 12, 40)
+        batch = synth.random_batch(seed, fst.num_ilabels, lens)
+        toks = batch.tokens.copy()
+        if toks.size > 3:
+            toks[3] = fst.num_ilabels  # a bad token
+        batch = synth.Batch(batch.offsets, toks)
+        d = wf.Fst.from_synth(fst, chunk_arcs=chunk, threads_per_sentence=nt, state_memory=3, checkpoint=ck)
+        assert_fb_parity(fst, batch, d, f"team seed={seed}")
+        assert d.health() == 0
 
 
 def test_tiny_integer_ties_global_state(wf):
