@@ -805,6 +805,60 @@ __device__ __forceinline__ double team_chunk(const DevLayout &L, const SliceInfo
     return lse_value_d(acc);
 }
 
+// Set v[key_j] = -inf for the keys j = first0, first0 + stride, ... < n of a
+// label's segments, four keys in flight at a time.
+__device__ __forceinline__ void team_clear(float *v, const int32_t *keys, int j0, int n, int stride)
+{
+    for (int j = j0; j < n; j += 4 * stride) {
+        int k[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) k[u] = j + u * stride < n ? keys[j + u * stride] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k[u] >= 0) v[k[u]] = WFST_NINF;
+    }
+}
+
+// K chunks at once (the lane's columns of K slices; on[k] false = no column):
+// all K chunks' row loads, then all their gathers, are in flight together.
+template <int K, int RB>
+__device__ __forceinline__ void team_chunks(const DevLayout &L, const SliceInfo (&sl)[K], const bool (&on)[K],
+                                            int lane, const float *u, double cprev, int32_t dead, double (&v)[K])
+{
+    LseD acc[K];
+    int h[K], hmax = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[k] = LseD{-__builtin_huge_val(), 0.0f};
+        h[k] = on[k] ? sl[k].height : 0;
+        hmax = max(hmax, h[k]);
+    }
+    for (int r0 = 0; r0 < hmax; r0 += RB) {
+        int32_t o[K][RB];
+        float sc[K][RB];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int at = sl[k].base + lane + (r0 + r) * sl[k].width;
+                o[k][r] = r0 + r < h[k] ? L.other[at] : dead;
+                sc[k][r] = r0 + r < h[k] ? L.score[at] : 0.0f;
+            }
+        float x[K][RB];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int r = 0; r < RB; ++r) x[k][r] = u[o[k][r]];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (x[k][r] != WFST_NINF) lse_push_d(acc[k], ((double)x[k][r] - cprev) + (double)sc[k][r]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = on[k] ? lse_value_d(acc[k]) : -__builtin_huge_val();
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT)
 team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ final_score, BatchView bv,
@@ -884,7 +938,7 @@ team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restri
                     o_first = lo.seg_first;
                     o_n = lo.n_segs;
                 }
-                for (int j = rank * NT + tid; j < o_n; j += G * NT) old[fl.seg_key[o_first + j]] = WFST_NINF;
+                team_clear(old, fl.seg_key + o_first, rank * NT + tid, o_n, G * NT);
             }
             if (tid == 0) s_cmax = 0ull;
             __syncthreads();
@@ -906,14 +960,28 @@ team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restri
                         }
                     }
                 }
-            for (int s = n_ms + rank * NW + wave; s < li.n_slices; s += G * NW) {
-                const SliceInfo si = fl.slice[li.slice_first + s];
-                if (lane < si.width) {
-                    const int c = s * 64 + lane;
-                    const int d = fl.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)];
-                    const double v = team_chunk<RB>(fl, si, lane, prev, cprev, Q);
-                    if (v != -__builtin_huge_val()) cur[d] = (float)v;
-                    my_max = fmax(my_max, v);
+            constexpr int KS = 4;  // slices per wavefront iteration (s, s + G*NW, ...): their loads overlap
+            for (int s = n_ms + rank * NW + wave; s < li.n_slices; s += KS * G * NW) {
+                SliceInfo sl[KS];
+                bool on[KS];
+                int d[KS];
+                double v[KS];
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const int sk = s + k * G * NW;
+                    sl[k] = sk < li.n_slices ? fl.slice[li.slice_first + sk] : SliceInfo{0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    on[k] = lane < sl[k].width;
+                    const int c = (s + k * G * NW) * 64 + lane;
+                    d[k] = on[k] ? fl.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)] : 0;
+                }
+                team_chunks<KS, 4>(fl, sl, on, lane, prev, cprev, Q, v);
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    if (v[k] != -__builtin_huge_val()) cur[d[k]] = (float)v[k];
+                    my_max = fmax(my_max, v[k]);
                 }
             }
             if (rank == 0) {
@@ -949,11 +1017,21 @@ team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restri
             } else {
                 tape = tp.alpha + bv.tok_off[i];
             }
-            if (tape)
-                for (int j = rank * NT + tid; j < li.n_segs; j += G * NT) {
-                    const float x = cur[fl.seg_key[li.seg_first + j]];
-                    to_global(tape)[j] = x == WFST_NINF ? WFST_NINF : (float)((double)x - c);
+            if (tape) {
+                const int stride = G * NT;
+                for (int j = rank * NT + tid; j < li.n_segs; j += 4 * stride) {  // four in flight
+                    int k[4];
+                    float x[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) k[u] = j + u * stride < li.n_segs ? fl.seg_key[li.seg_first + j + u * stride] : Q;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) x[u] = cur[k[u]];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (j + u * stride < li.n_segs)
+                            to_global(tape)[j + u * stride] = x[u] == WFST_NINF ? WFST_NINF : (float)((double)x[u] - c);
                 }
+            }
             if (rank == 0 && tid == 0 && bk.c == 0) {
                 tp.a_max[i] = 0.0f;
                 tp.a_log[i] = C;
@@ -1023,7 +1101,7 @@ team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restri
                     t_first = lt.seg_first;
                     t_n = lt.n_segs;
                 }
-                for (int j = rank * NT + tid; j < t_n; j += G * NT) v[fl.seg_key[t_first + j]] = WFST_NINF;
+                team_clear(v, fl.seg_key + t_first, rank * NT + tid, t_n, G * NT);
             }
         }
         if (!team_sync(tv, team, ++nbar, bv.health)) return;
