@@ -33,13 +33,21 @@ def _lse2(a, b):
     return out
 
 
-def lattice_forward(fst, n_nodes, arcs):
+def label_index(fst):
+    """(order, bounds): the FST's arc ids stably sorted by input label, and
+    where each label's run starts (label a: order[bounds[a]:bounds[a+1]])."""
+    order = np.argsort(np.asarray(fst.ilabel), kind="stable")
+    bounds = np.searchsorted(np.asarray(fst.ilabel)[order], np.arange(fst.num_ilabels + 1))
+    return order, bounds
+
+
+def lattice_forward(fst, n_nodes, arcs, index=None):
     """(log Z, node vectors f64[n_nodes, Q]) of one lattice; arcs = list of
-    (u, v, label, log weight) with u < v < n_nodes, label in [-1, M)."""
+    (u, v, label, log weight) with u < v < n_nodes, label in [-1, M).
+    index: label_index(fst), when the caller reuses it over many lattices."""
     Q = fst.num_states
-    by_label = {}
-    for k in range(fst.num_arcs):
-        by_label.setdefault(int(fst.ilabel[k]), []).append(k)
+    order, bounds = index if index is not None else label_index(fst)
+    by_label = {a: order[bounds[a]:bounds[a + 1]] for a in {int(e[2]) for e in arcs if e[2] >= 0}}
     A = np.full((n_nodes, Q), -np.inf)
     A[0, fst.start] = 0.0
     for v in range(1, n_nodes):
