@@ -13,6 +13,8 @@ struct DevLayout {
     int32_t *other = nullptr;      // padded, slice-interleaved arc slots: other end state
     float *score = nullptr;        // ... and arc score
     int32_t *elem_arc = nullptr;   // arc id per slot (-1 padding)
+    uint16_t *elem_loc = nullptr;  // arc id - its label's lowest arc id (0xffff: padding or too far), for
+                                   // score updates staged per label; null when they are not staged
     SliceInfo *slice = nullptr;
     int32_t *seg_key = nullptr;
     SegChunk *seg_chunk = nullptr;

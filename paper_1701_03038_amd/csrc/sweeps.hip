@@ -2418,25 +2418,53 @@ constexpr int kScoreStage = 10112;  // floats (39.5 KiB of LDS: four workgroups 
 
 constexpr int kScoreUnroll = 8;  // elements per thread in flight
 
+// elem_loc of a layout: for every slot of a slice, its arc's offset from the
+// lowest arc id of the slice's label (0xffff for padding, or when a label's
+// arcs span 0xffff ids or more: such labels are never staged).
+__global__ void build_elem_loc(const SliceInfo *__restrict__ slice, int64_t n_slice, const int32_t *__restrict__ elem_arc,
+                               const int2 *__restrict__ range, uint16_t *__restrict__ loc)
+{
+    for (int64_t s = blockIdx.x; s < n_slice; s += gridDim.x) {
+        const SliceInfo si = slice[s];
+        const int lo = range[si.label].x;
+        const int n = si.height * si.width;
+        for (int x = threadIdx.x; x < n; x += blockDim.x) {
+            const int arc = elem_arc[si.base + x];
+            const int d = arc - lo;
+            loc[si.base + x] = (uint16_t)(arc >= 0 && d >= 0 && d < 0xffff ? d : 0xffff);
+        }
+    }
+}
+
 template <bool STAGED>  // scores from the LDS stage, else from global memory (kept apart: no generic loads)
 __device__ __forceinline__ void scatter_label_layout(const LabelInfo &li, float *__restrict__ out,
-                                                     const int32_t *__restrict__ elem_arc, const float *stage,
-                                                     int32_t lo, const float *__restrict__ score)
+                                                     const int32_t *__restrict__ elem_arc,
+                                                     const uint16_t *__restrict__ elem_loc, const float *stage,
+                                                     const float *__restrict__ score)
 {
     const int32_t *ea = elem_arc + li.elem_first;
+    const uint16_t *el = elem_loc + li.elem_first;
     float *o = out + li.elem_first;
     for (int e0 = threadIdx.x; e0 < li.n_elems; e0 += kScoreUnroll * kScoreThreads) {
-        int arc[kScoreUnroll];
-#pragma unroll
-        for (int u = 0; u < kScoreUnroll; ++u) {
-            const int e = e0 + u * kScoreThreads;
-            arc[u] = e < li.n_elems ? ea[e] : -1;
-        }
         float v[kScoreUnroll];
+        if constexpr (STAGED) {  // 2-byte offsets into the label's staged scores
+            int loc[kScoreUnroll];
 #pragma unroll
-        for (int u = 0; u < kScoreUnroll; ++u) {
-            v[u] = 0.0f;  // padding keeps score 0
-            if (arc[u] >= 0) v[u] = STAGED ? stage[arc[u] - lo] : score[arc[u]];
+            for (int u = 0; u < kScoreUnroll; ++u) {
+                const int e = e0 + u * kScoreThreads;
+                loc[u] = e < li.n_elems ? (int)el[e] : 0xffff;
+            }
+#pragma unroll
+            for (int u = 0; u < kScoreUnroll; ++u) v[u] = loc[u] != 0xffff ? stage[loc[u]] : 0.0f;  // padding: 0
+        } else {
+            int arc[kScoreUnroll];
+#pragma unroll
+            for (int u = 0; u < kScoreUnroll; ++u) {
+                const int e = e0 + u * kScoreThreads;
+                arc[u] = e < li.n_elems ? ea[e] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kScoreUnroll; ++u) v[u] = arc[u] >= 0 ? score[arc[u]] : 0.0f;  // padding: 0
         }
 #pragma unroll
         for (int u = 0; u < kScoreUnroll; ++u) {
@@ -2449,7 +2477,8 @@ __device__ __forceinline__ void scatter_label_layout(const LabelInfo &li, float 
 __global__ void __launch_bounds__(kScoreThreads)
 scatter_scores_by_label(const LabelInfo *__restrict__ fl, const LabelInfo *__restrict__ rl,
                         const int2 *__restrict__ range, float *__restrict__ out_f, const int32_t *__restrict__ arc_f,
-                        float *__restrict__ out_r, const int32_t *__restrict__ arc_r,
+                        const uint16_t *__restrict__ loc_f, float *__restrict__ out_r,
+                        const int32_t *__restrict__ arc_r, const uint16_t *__restrict__ loc_r,
                         const float *__restrict__ score)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -2475,11 +2504,11 @@ scatter_scores_by_label(const LabelInfo *__restrict__ fl, const LabelInfo *__res
     }
     __syncthreads();
     if (staged) {
-        scatter_label_layout<true>(fl[a], out_f, arc_f, stage, r.x, score);
-        scatter_label_layout<true>(rl[a], out_r, arc_r, stage, r.x, score);
+        scatter_label_layout<true>(fl[a], out_f, arc_f, loc_f, stage, score);
+        scatter_label_layout<true>(rl[a], out_r, arc_r, loc_r, stage, score);
     } else {
-        scatter_label_layout<false>(fl[a], out_f, arc_f, stage, r.x, score);
-        scatter_label_layout<false>(rl[a], out_r, arc_r, stage, r.x, score);
+        scatter_label_layout<false>(fl[a], out_f, arc_f, loc_f, stage, score);
+        scatter_label_layout<false>(rl[a], out_r, arc_r, loc_r, stage, score);
     }
 }
 

@@ -236,10 +236,26 @@ void free_owned(wfst_fst *f, void *p)
 
 void free_layout(wfst_fst *f, DevLayout &d)
 {
-    for (void *p : {(void *)d.other, (void *)d.score, (void *)d.elem_arc, (void *)d.slice, (void *)d.seg_key,
-                    (void *)d.seg_chunk, (void *)d.label})
+    for (void *p : {(void *)d.other, (void *)d.score, (void *)d.elem_arc, (void *)d.elem_loc, (void *)d.slice,
+                    (void *)d.seg_key, (void *)d.seg_chunk, (void *)d.label})
         free_owned(f, p);
     d = DevLayout();
+}
+
+// The 2-byte label-relative arc offsets of both layouts, for score updates
+// staged per label (built when the FST's labels are staged).
+int build_elem_locs(wfst_fst *f, hipStream_t s)
+{
+    if (!f->stage_scores) return WFST_OK;
+    for (DevLayout *d : {&f->fwd, &f->rev}) {
+        if (d->n_elem == 0) continue;
+        TRY(dev_upload<uint16_t>(f, &d->elem_loc, nullptr, d->n_elem, s));
+        hipLaunchKernelGGL(build_elem_loc, dim3(grid_for(d->n_slice, 1, 65535)), dim3(256), 0, s,
+                           (const SliceInfo *)d->slice, d->n_slice, (const int32_t *)d->elem_arc,
+                           (const int2 *)f->label_range, d->elem_loc);
+    }
+    HIP_OK(hipGetLastError());
+    return WFST_OK;
 }
 
 void free_buf(Buf &b)
@@ -957,6 +973,7 @@ int rebuild_layouts(wfst_fst *f, int32_t chunk, hipStream_t s)
     free_layout(f, f->rev);
     TRY(upload_layout(f, hf, f->fwd, s));
     TRY(upload_layout(f, hr, f->rev, s));
+    TRY(build_elem_locs(f, s));
     HIP_OK(hipStreamSynchronize(s));
     f->chunk = chunk;
     f->score_version += 1;  // tapes made on the old layouts are not used again
@@ -1243,6 +1260,7 @@ int wfst_fst_create(int32_t num_states, int32_t num_ilabels, int32_t start, int6
             }
             f->stage_scores = num_arcs > 0 && num_arcs / num_ilabels >= 256 && 2 * staged_arcs >= num_arcs;
             rc = dev_upload(f, &f->label_range, range.data(), num_ilabels, s);
+            if (rc == WFST_OK) rc = build_elem_locs(f, s);
         }
         if (rc == WFST_OK) {
             hipLaunchKernelGGL(final_max_kernel, dim3(1), dim3(1024), 0, s, (const float *)f->final_score, f->Q,
@@ -1278,8 +1296,8 @@ int wfst_fst_set_scores(wfst_fst *f, const float *arc_score_dev, const float *fi
             hipLaunchKernelGGL(scatter_scores_by_label, dim3((unsigned)f->M), dim3(kScoreThreads),
                                kScoreStage * sizeof(float), s, (const LabelInfo *)f->fwd.label,
                                (const LabelInfo *)f->rev.label, (const int2 *)f->label_range, f->fwd.score,
-                               (const int32_t *)f->fwd.elem_arc, f->rev.score, (const int32_t *)f->rev.elem_arc,
-                               arc_score_dev);
+                               (const int32_t *)f->fwd.elem_arc, (const uint16_t *)f->fwd.elem_loc, f->rev.score,
+                               (const int32_t *)f->rev.elem_arc, (const uint16_t *)f->rev.elem_loc, arc_score_dev);
         } else {
             hipLaunchKernelGGL(scatter_scores, dim3((unsigned)tiles), dim3(256), 0, s, f->fwd.score,
                                (const int32_t *)f->fwd.elem_arc, f->fwd.n_elem, f->rev.score,
