@@ -1564,9 +1564,10 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                             if (nrec > 0 && !stage) {
 #pragma unroll
                                 for (int u = 0; u < RB; ++u) {
-                                    if (v[u] == 0.0f) continue;
-                                    const int arc = arc_of[u];
-                                    atomicAdd(&rs.acc[arc], (unsigned long long)__double2ll_rn((double)v[u] * fx));
+                                    // posteriors that round to 0 at the accumulators' scale add nothing
+                                    const long long q = __double2ll_rn((double)v[u] * fx);
+                                    if (q == 0) continue;
+                                    atomicAdd(&rs.acc[arc_of[u]], (unsigned long long)q);
                                 }
                             } else if (nrec > 0) {
                                 int at = wave_append(nrec, &s_rn, lane);
