@@ -2737,6 +2737,7 @@ struct LatticeView {
     const float *weight = nullptr;
     float *nodes = nullptr;   // [n_nodes * (Q+1)] normalised vectors (entry Q = -inf)
     double *scale = nullptr;  // [n_nodes]
+    int32_t *far = nullptr;   // [n_nodes] zero at launch; 1: an arc leaves the node for a node beyond the next
     int32_t *queue = nullptr;
     const int32_t *offs_bad = nullptr;  // set by lattice_offsets_check
 };
@@ -2766,8 +2767,10 @@ lattice_forward(DevLayout fl, int32_t Q, int32_t start, int32_t M, const float *
     double *vval = acc + (Q + 1);                             // [max_segs]
     double *part = vval + max(fl.max_segs, 1);                // [max_slots]
     int32_t *vkey = reinterpret_cast<int32_t *>(part + max(fl.max_slots, 1));  // [max_segs]
+    float *pvec = reinterpret_cast<float *>(vkey + max(fl.max_segs, 1));      // [Q+1] the previous node, normalised
     __shared__ int s_item;
     __shared__ unsigned long long s_cmax;
+    __shared__ double s_pscale;  // the previous node's scale
     __shared__ double s_rm[NW];
     __shared__ float s_rs[NW];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -2806,9 +2809,39 @@ lattice_forward(DevLayout fl, int32_t Q, int32_t start, int32_t M, const float *
             }
             continue;
         }
-        for (int64_t q = tid; q < Q1; q += NT) lv.nodes[(int64_t)n0 * Q1 + q] = q == start ? 0.0f : WFST_NINF;
-        if (tid == 0) lv.scale[n0] = 0.0;
+        // Node vectors stay on chip while only the next node reads them; a node that
+        // an arc leaves for a node further ahead is also kept in HBM.
+        for (int e = a0 + tid; e < a1; e += NT)
+            if (lv.to[e] > lv.from[e] + 1) lv.far[n0 + lv.from[e]] = 1;
+        for (int64_t q = tid; q < Q1; q += NT) {
+            const float x = q == start ? 0.0f : WFST_NINF;
+            pvec[q] = x;
+            if (node_alpha && q < Q) node_alpha[(int64_t)n0 * Q + q] = x;
+        }
+        if (tid == 0) s_pscale = 0.0;
         __syncthreads();
+        if (lv.far[n0]) {
+            for (int64_t q = tid; q < Q1; q += NT) lv.nodes[(int64_t)n0 * Q1 + q] = pvec[q];
+            if (tid == 0) lv.scale[n0] = 0.0;
+        }
+        // one incoming arc merged into acc: epsilon (log-add of the source vector) or
+        // a log-semiring step of the label's forward layout; prev is on chip or in HBM
+        auto merge_arc = [&](const float *prev, double cu, int a) {
+            if (a < 0) {
+                for (int q = tid; q < Q; q += NT) {
+                    const float x = prev[q];
+                    if (x != WFST_NINF) acc[q] = log_add_d(acc[q], (double)x + cu);
+                }
+            } else {
+                const LabelInfo li = uniform_label(fl.label[a]);
+                (void)lse_step<NT, 8>(fl, li, prev, part, vval, vkey, lane, wave, Q);
+                __syncthreads();
+                for (int j = tid; j < li.n_segs; j += NT) {  // distinct keys: no two threads share one
+                    const double x = vval[j];
+                    if (x != -__builtin_huge_val()) acc[vkey[j]] = log_add_d(acc[vkey[j]], x + cu);
+                }
+            }
+        };
         int e = a0;
         for (int v = 1; v < n; ++v) {
             for (int64_t q = tid; q < Q1; q += NT) acc[q] = -__builtin_huge_val();
@@ -2817,22 +2850,10 @@ lattice_forward(DevLayout fl, int32_t Q, int32_t start, int32_t M, const float *
             for (; e < a1 && lv.to[e] == v; ++e) {  // incoming arcs, in their order
                 const int u = lv.from[e], a = lv.label[e];
                 const double w = (double)lv.weight[e];
-                const float *prev = lv.nodes + (int64_t)(n0 + u) * Q1;
-                const double cu = lv.scale[n0 + u] + w;
-                if (a < 0) {
-                    for (int q = tid; q < Q; q += NT) {
-                        const float x = prev[q];
-                        if (x != WFST_NINF) acc[q] = log_add_d(acc[q], (double)x + cu);
-                    }
-                } else {
-                    const LabelInfo li = uniform_label(fl.label[a]);
-                    (void)lse_step<NT, 8>(fl, li, prev, part, vval, vkey, lane, wave, Q);
-                    __syncthreads();
-                    for (int j = tid; j < li.n_segs; j += NT) {  // distinct keys: no two threads share one
-                        const double x = vval[j];
-                        if (x != -__builtin_huge_val()) acc[vkey[j]] = log_add_d(acc[vkey[j]], x + cu);
-                    }
-                }
+                if (u == v - 1)
+                    merge_arc(pvec, s_pscale + w, a);
+                else
+                    merge_arc(lv.nodes + (int64_t)(n0 + u) * Q1, lv.scale[n0 + u] + w, a);
                 __syncthreads();
             }
             double mx = -__builtin_huge_val();
@@ -2841,24 +2862,25 @@ lattice_forward(DevLayout fl, int32_t Q, int32_t start, int32_t M, const float *
             __syncthreads();
             double c = unord_f64(s_cmax);
             if (!(c > -__builtin_huge_val())) c = 0.0;
+            const bool keep = lv.far[n0 + v] != 0;
             float *node = lv.nodes + (int64_t)(n0 + v) * Q1;
-            for (int64_t q = tid; q < Q1; q += NT)
-                node[q] = acc[q] == -__builtin_huge_val() ? WFST_NINF : (float)(acc[q] - c);
-            if (tid == 0) lv.scale[n0 + v] = c;
+            for (int64_t q = tid; q < Q1; q += NT) {
+                const double y = acc[q];
+                const float x = y == -__builtin_huge_val() ? WFST_NINF : (float)(y - c);
+                pvec[q] = x;
+                if (keep) node[q] = x;
+                if (node_alpha && q < Q) node_alpha[(int64_t)(n0 + v) * Q + q] = y == -__builtin_huge_val() ? WFST_NINF : (float)y;
+            }
+            if (tid == 0) {
+                s_pscale = c;
+                if (keep) lv.scale[n0 + v] = c;
+            }
             __syncthreads();
         }
-        if (node_alpha)
-            for (int64_t x = tid; x < (int64_t)n * Q; x += NT) {
-                const int64_t v = x / Q, q = x - v * Q;
-                const float y = lv.nodes[(n0 + v) * Q1 + q];
-                node_alpha[(n0 + v) * (int64_t)Q + q] =
-                    y == WFST_NINF ? WFST_NINF : (float)((double)y + lv.scale[n0 + v]);
-            }
-        // log Z = C_end + LSE_q(A^_end[q] + f[q])
-        const float *last = lv.nodes + (int64_t)(n1 - 1) * Q1;
+        // log Z = C_end + LSE_q(A^_end[q] + f[q]) (the last node is on chip)
         LseD z{-__builtin_huge_val(), 0.0f};
         for (int q = tid; q < Q; q += NT) {
-            const float x = last[q], f = final_score[q];
+            const float x = pvec[q], f = final_score[q];
             if (x == WFST_NINF || f == WFST_NINF) continue;
             lse_push_d(z, (double)x + (double)f);
         }
@@ -2875,7 +2897,7 @@ lattice_forward(DevLayout fl, int32_t Q, int32_t start, int32_t M, const float *
             const double lzr = lse_value_d(tot);
             const bool ok = lzr != -__builtin_huge_val();
             status[b] = ok ? WFST_STATUS_OK : WFST_STATUS_NO_PATH;
-            log_z[b] = ok ? (float)(lv.scale[n1 - 1] + lzr) : WFST_NINF;
+            log_z[b] = ok ? (float)(s_pscale + lzr) : WFST_NINF;
         }
         __syncthreads();
     }

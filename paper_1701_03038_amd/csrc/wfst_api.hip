@@ -96,7 +96,7 @@ enum WsSlot {
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
     W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_SCAN0,
-    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_TVEC, W_TPMAX, W_TPZ, W_TPART, W_TBAR, W_NUM
+    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_TVEC, W_TPMAX, W_TPZ, W_TPART, W_TBAR, W_LATFAR, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
@@ -1989,7 +1989,7 @@ size_t lds_lattice(const wfst_fst *f)
 {
     return ((size_t)f->Q + 1 + (size_t)std::max(f->fwd.max_segs, 1) + (size_t)std::max(f->fwd.max_slots, 1)) *
                sizeof(double) +
-           (size_t)std::max(f->fwd.max_segs, 1) * sizeof(int32_t);
+           (size_t)std::max(f->fwd.max_segs, 1) * sizeof(int32_t) + ((size_t)f->Q + 1) * sizeof(float);
 }
 
 int wfst_lattice_forward(const wfst_fst *fc, int32_t batch, const int32_t *node_offsets, const int32_t *arc_offsets,
@@ -2017,7 +2017,11 @@ int wfst_lattice_forward(const wfst_fst *fc, int32_t batch, const int32_t *node_
     TRY(ensure_t(f->ws[W_COUNTERS], C_COUNT, s, &counters));
     TRY(ensure_t(f->ws[W_LATNODE], std::max<int64_t>(num_nodes, 1) * Q1, s, &nodes));
     TRY(ensure_t(f->ws[W_LATSCALE], std::max<int64_t>(num_nodes, 1), s, &scale));
+    int32_t *far = nullptr;
+    TRY(ensure_t(f->ws[W_LATFAR], std::max<int64_t>(num_nodes, 1), s, &far));
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
+    hipLaunchKernelGGL(fill_i32, dim3(grid_for(std::max<int64_t>(num_nodes, 1), 256, 8192)), dim3(256), 0, s, far,
+                       std::max<int64_t>(num_nodes, 1), 0);
     LatticeView lv;
     lv.B = batch;
     lv.n_nodes = num_nodes;
@@ -2030,6 +2034,7 @@ int wfst_lattice_forward(const wfst_fst *fc, int32_t batch, const int32_t *node_
     lv.weight = arc_weight;
     lv.nodes = nodes;
     lv.scale = scale;
+    lv.far = far;
     lv.queue = counters + C_QUEUE;
     lv.offs_bad = counters + C_NITEMS;
     hipLaunchKernelGGL(lattice_offsets_check, dim3(grid_for((int64_t)batch + 1, 256)), dim3(256), 0, s, node_offsets,
