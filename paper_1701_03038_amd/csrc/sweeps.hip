@@ -2724,9 +2724,10 @@ __global__ void scan_finish(const float *__restrict__ P, const int32_t *__restri
 // =====================================================================
 __device__ __forceinline__ double log_add_d(double a, double b)
 {
+    if (a == -__builtin_huge_val()) return b;  // the first contribution: nothing to add
+    if (b == -__builtin_huge_val()) return a;
     const double m = fmax(a, b);
-    if (m == -__builtin_huge_val()) return m;
-    return m + log(exp(a - m) + exp(b - m));
+    return m + log1p(exp(fmin(a, b) - m));
 }
 
 struct LatticeView {
