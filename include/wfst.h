@@ -182,6 +182,13 @@ int wfst_fst_profile_read(wfst_fst *fst, double *ms, int64_t *launches, int32_t 
  * stream); clear != 0 resets the word afterwards.  0 means healthy. */
 int wfst_fst_health(const wfst_fst *fst, uint32_t *flags, int32_t clear, void *stream);
 
+/* Testing hook for failure handling: the number of polls a team sweep's
+ * barrier wait makes before the team stops (health bit 64); 0 restores the
+ * default (2^24).  A small limit makes a team stop at its first barrier that
+ * is not passed at once, so that the timeout path can be exercised without
+ * any wait that does not end. */
+int wfst_fst_debug_team_spin(wfst_fst *fst, int32_t polls);
+
 /*
  * Viterbi decoding of a batch (paper, Algorithm 1 + section 5.1).
  * Outputs (caller-owned DEVICE memory):

@@ -85,7 +85,7 @@ EXPORTS = (
     "wfst_forward_backward", "wfst_last_error", "wfst_layout_host", "wfst_fst_autotune",
     "wfst_fst_score_version", "wfst_viterbi_noalloc", "wfst_graph_create", "wfst_graph_launch",
     "wfst_graph_destroy", "wfst_em_update", "wfst_att_parse", "wfst_att_last_error", "wfst_forward_scan",
-    "wfst_lattice_forward",
+    "wfst_lattice_forward", "wfst_fst_debug_team_spin",
 )
 
 
@@ -128,6 +128,7 @@ def load_library(path: str | None = None):
     lib.wfst_em_update.argtypes = [P, P, ctypes.c_float, P, P, P]
     lib.wfst_forward_scan.argtypes = [P, i32, i64, P, P, P, P, P, P]
     lib.wfst_lattice_forward.argtypes = [P, i32, P, P, i64, i64, P, P, P, P, P, P, P, P]
+    lib.wfst_fst_debug_team_spin.argtypes = [P, i32]
     lib.wfst_att_parse.argtypes = [ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.c_char_p, i64, i32, P,
                                    P, P, P, P, P, P]
     lib.wfst_att_parse.restype = ctypes.c_int
@@ -138,7 +139,7 @@ def load_library(path: str | None = None):
                  "wfst_fst_label_stats", "wfst_viterbi", "wfst_viterbi_noalloc",
                  "wfst_forward", "wfst_backward", "wfst_forward_backward", "wfst_layout_host",
                  "wfst_fst_autotune", "wfst_graph_create", "wfst_graph_launch", "wfst_em_update",
-                 "wfst_forward_scan", "wfst_lattice_forward"):
+                 "wfst_forward_scan", "wfst_lattice_forward", "wfst_fst_debug_team_spin"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -247,6 +248,10 @@ class Fst:
         out = ctypes.c_uint32(0)
         _check(_lib.wfst_fst_health(self.handle, ctypes.byref(out), int(clear), _stream()))
         return int(out.value)
+
+    def debug_team_spin(self, polls: int) -> None:
+        """Testing hook: poll limit of the team sweep's barrier waits (0 = default)."""
+        _check(_lib.wfst_fst_debug_team_spin(self.handle, int(polls)))
 
     def score_version(self) -> int:
         """Number of score updates so far (a tape only serves backward at the version it was made at)."""

@@ -730,7 +730,7 @@ forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
 // the stored state is alpha_t - C_{t-1} (the step max is known only after the
 // barrier) and the step's normaliser is subtracted when it is read.
 // =====================================================================
-constexpr int kTeamSpin = 1 << 24;  // polls per barrier wait before the team gives up
+constexpr int kTeamSpin = 1 << 24;  // default polls per barrier wait before the team gives up
 
 struct TeamView {
     int32_t G = 0;                  // workgroups per team (grid = G * n_teams)
@@ -742,6 +742,7 @@ struct TeamView {
     double *part = nullptr;         // [n_teams][max_slots] chunk values of multi-chunk segments (rank 0)
     unsigned int *bar = nullptr;    // [n_teams] barrier counters, zero at launch
     int32_t *abort = nullptr;       // set when a member times out; every member then stops
+    int32_t spin_limit = kTeamSpin; // polls per barrier wait before the team gives up
 };
 
 // Team barrier number k (counted from 1): thread 0 of each member announces
@@ -763,7 +764,7 @@ __device__ __forceinline__ bool team_sync(const TeamView &tv, int team, unsigned
                 ok = 0;
                 break;
             }
-            if (spin >= kTeamSpin) {
+            if (spin >= tv.spin_limit) {
                 atomicOr(health, H_TEAM);
                 atomicExch(tv.abort, 1);
                 ok = 0;

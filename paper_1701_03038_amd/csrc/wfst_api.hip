@@ -145,6 +145,7 @@ struct wfst_fst {
     int cu_count = 0;
     size_t max_lds = 0;
     bool coop = false;  // cooperative launches supported (team sweeps)
+    int32_t team_spin = 0;  // team barrier poll limit (0: the default)
     std::vector<std::pair<void *, size_t>> allocs;  // owned device arrays and their bytes
     Buf ws[W_NUM];
     std::vector<TapeBufs *> tape_pool;
@@ -589,6 +590,7 @@ int launch_team_forward(wfst_fst *f, hipStream_t s, const BatchView &bv, const T
     TeamView tv;
     tv.G = G;
     tv.n_teams = kTeamsPerDevice;
+    if (f->team_spin > 0) tv.spin_limit = f->team_spin;
     tv.q1 = ((int64_t)f->Q + 1 + 63) / 64 * 64;
     unsigned int *bar = nullptr;
     TRY(ensure_t(f->ws[W_TVEC], (int64_t)tv.n_teams * 3 * tv.q1, s, &tv.vec));
@@ -1353,6 +1355,14 @@ int wfst_fst_profile_read(wfst_fst *f, double *ms, int64_t *launches, int32_t re
         for (auto &m : f->marks) f->spare.push_back(m);
         f->marks.clear();
     }
+    return WFST_OK;
+}
+
+int wfst_fst_debug_team_spin(wfst_fst *f, int32_t polls)
+{
+    if (!f) return set_err(WFST_EINVAL, "fst is NULL");
+    if (polls < 0) return set_err(WFST_EINVAL, "polls must be >= 0");
+    f->team_spin = polls;
     return WFST_OK;
 }
 

@@ -76,6 +76,26 @@ def test_tiny_team_forward(wf, chunk, nt, ck):
         assert d.health() == 0
 
 
+def test_team_barrier_timeout_is_reported(wf):
+    """Failure handling of the team sweep, forced from the host: with a poll
+    limit of 1 a team stops at the first barrier its members do not pass at
+    once; the call returns, health bit 64 reports it.  With the default limit
+    again the same FST computes the right results."""
+    import torch
+    say("case: team barrier timeout (poll limit 1)")
+    fst = synth.tiny_random_fst(351, 5, 2, 18, final_prob=0.8)
+    batch = synth.random_batch(351, fst.num_ilabels, np.random.default_rng(351).integers(1, 10, 64))
+    d = wf.Fst.from_synth(fst, state_memory=3)
+    d.debug_team_spin(1)
+    lz, st, tape = wf.forward(d, batch.offsets, batch.tokens)
+    torch.cuda.synchronize()
+    tape.free()
+    assert d.health(clear=True) & 64, "a team with a poll limit of 1 should have stopped"
+    d.debug_team_spin(0)
+    assert_fb_parity(fst, batch, d, "team after a stopped run")
+    assert d.health() == 0
+
+
 def test_tiny_integer_ties_global_state(wf):
     """Integer scores (dense ties): the lowest-arc-id path, bit for bit."""
     for seed in range(320, 330):
