@@ -743,6 +743,7 @@ struct TeamView {
     unsigned int *bar = nullptr;    // [n_teams] barrier counters, zero at launch
     int32_t *abort = nullptr;       // set when a member times out; every member then stops
     int32_t spin_limit = kTeamSpin; // polls per barrier wait before the team gives up
+    int32_t *work = nullptr;        // [n_teams][2] slice-group counters, by step parity
 };
 
 // Team barrier number k (counted from 1): thread 0 of each member announces
@@ -921,6 +922,7 @@ team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restri
             const float *ta = tp.alpha + tp.ck_off[ic];
             for (int j = rank * NT + tid; j < lc_n; j += G * NT) v0[fl.seg_key[lc_first + j]] = ta[j];
         }
+        if (rank == 0 && tid < 2) tv.work[2 * team + tid] = 0;
         if (!team_sync(tv, team, ++nbar, bv.health)) return;
         double C = 0.0, cprev = 0.0;
         for (int t = t0 + 1; t <= t1; ++t) {
@@ -961,21 +963,30 @@ team_forward_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restri
                         }
                     }
                 }
-            constexpr int KS = 4;  // slices per wavefront iteration (s, s + G*NW, ...): their loads overlap
-            for (int s = n_ms + rank * NW + wave; s < li.n_slices; s += KS * G * NW) {
+            // the other slices, in groups of KS taken from the team's counter by each
+            // wavefront (dynamic, so that members finish together); a group's row
+            // loads and gathers are in flight together
+            constexpr int KS = 4;
+            if (rank == 0 && tid == 0) tv.work[2 * team + ((t + 1) & 1)] = 0;  // the counter of step t+1
+            for (;;) {
+                int grp = 0;
+                if (lane == 0) grp = atomicAdd(&tv.work[2 * team + (t & 1)], 1);
+                grp = __shfl(grp, 0, 64);
+                const int s0 = n_ms + grp * KS;
+                if (s0 >= li.n_slices) break;
                 SliceInfo sl[KS];
                 bool on[KS];
                 int d[KS];
                 double v[KS];
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
-                    const int sk = s + k * G * NW;
+                    const int sk = s0 + k;
                     sl[k] = sk < li.n_slices ? fl.slice[li.slice_first + sk] : SliceInfo{0, 0, 0, 0};
                 }
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
                     on[k] = lane < sl[k].width;
-                    const int c = (s + k * G * NW) * 64 + lane;
+                    const int c = (s0 + k) * 64 + lane;
                     d[k] = on[k] ? fl.seg_key[li.seg_first + li.n_multi + (c - li.n_slots)] : 0;
                 }
                 team_chunks<KS, 4>(fl, sl, on, lane, prev, cprev, Q, v);

@@ -96,7 +96,7 @@ enum WsSlot {
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
     W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_SCAN0,
-    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_TVEC, W_TPMAX, W_TPZ, W_TPART, W_TBAR, W_LATFAR, W_NUM
+    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_TVEC, W_TPMAX, W_TPZ, W_TPART, W_TBAR, W_LATFAR, W_TWORK, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
@@ -598,9 +598,11 @@ int launch_team_forward(wfst_fst *f, hipStream_t s, const BatchView &bv, const T
     TRY(ensure_t(f->ws[W_TPZ], (int64_t)tv.n_teams * 2 * G, s, &tv.pz));
     TRY(ensure_t(f->ws[W_TPART], (int64_t)tv.n_teams * std::max(f->fwd.max_slots, 1), s, &tv.part));
     TRY(ensure_t(f->ws[W_TBAR], (int64_t)tv.n_teams + 1, s, &bar));
+    TRY(ensure_t(f->ws[W_TWORK], (int64_t)tv.n_teams * 2, s, &tv.work));
     tv.bar = bar;
     tv.abort = reinterpret_cast<int32_t *>(bar + tv.n_teams);
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int32_t *>(bar), (int64_t)tv.n_teams + 1, 0);
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, tv.work, (int64_t)tv.n_teams * 2, 0);
     ProfScope prof(f, s, WFST_KERNEL_FORWARD);
     DevLayout fl = f->fwd;
     int32_t Q = f->Q, start = f->start;
