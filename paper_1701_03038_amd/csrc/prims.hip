@@ -141,41 +141,48 @@ __global__ void __launch_bounds__(1024) order_by_length(const int32_t *__restric
 
 // ---------------------------------------------------------------------
 // Stable LSD radix sort of (key, value) pairs (int32 or uint64 keys, int32
-// values), 8 bits per pass.
-// Tile = 1024 elements per block of 256 threads (4 per thread, consecutive).
+// values), 8 bits per pass.  A uint64 key hi:lo with lo < 2^pb is sorted as
+// the packed value (hi << pb) | lo, so that hi and lo need only their own
+// significant bits between them (pb = 32: the key as it is).
+// Tile = 1024 elements per block of 256 threads; each wavefront scatters a
+// contiguous quarter of it.
 // ---------------------------------------------------------------------
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
-__device__ __forceinline__ int digit_of(int32_t key, int shift) { return ((uint32_t)key >> shift) & 0xff; }
-__device__ __forceinline__ int digit_of(uint64_t key, int shift) { return (int)((key >> shift) & 0xff); }
+__device__ __forceinline__ int digit_of(int32_t key, int shift, int) { return ((uint32_t)key >> shift) & 0xff; }
+__device__ __forceinline__ int digit_of(uint64_t key, int shift, int pb)
+{
+    const uint64_t packed = ((key >> 32) << pb) | (key & 0xffffffffull);
+    return (int)((packed >> shift) & 0xff);
+}
 
 // hist[d * ntiles + tile] = occurrences of digit d in the tile
 template <class K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, int64_t n, int shift,
-                                                           int64_t ntiles, int64_t *__restrict__ hist)
+                                                           int pb, int64_t ntiles, int64_t *__restrict__ hist)
 {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t i = base + (int64_t)threadIdx.x * kSortItems + k;
-        if (i < n) atomicAdd(&h[digit_of(keys[i], shift)], 1);
+        const int64_t i = base + (int64_t)k * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[digit_of(keys[i], shift, pb)], 1);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
 // Scatter with the scanned histogram (digit-major, tile-minor).  Wave w of a
-// tile owns elements [256w, 256w+256) in four rounds of 64 consecutive
-// elements; a lane's rank among equal digits before it comes from matching
+// tile owns elements [64 I w, 64 I (w+1)) (I = kSortItems) in I rounds of 64
+// consecutive elements; a lane's rank among equal digits before it comes from matching
 // its digit against the wave with 8 ballots, so every pass is stable.
 template <class K>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restrict__ keys_in,
                                                               const int32_t *__restrict__ vals_in, int64_t n,
-                                                              int shift, int64_t ntiles,
+                                                              int shift, int pb, int64_t ntiles,
                                                               const int64_t *__restrict__ offs,
                                                               K *__restrict__ keys_out,
                                                               int32_t *__restrict__ vals_out,
@@ -186,20 +193,22 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restric
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int j = 0; j < 4; ++j) wcnt[wave][lane + 64 * j] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * 256;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * 64 * kSortItems;
     const unsigned long long lt = (1ull << lane) - 1ull;
     int dg[kSortItems], rank[kSortItems];
     K kv[kSortItems];
     int32_t vv[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {  // every round's loads in flight before the ranking
+        const int64_t i = base + k * 64 + lane;
+        kv[k] = i < n ? keys_in[i] : K(0);
+        vv[k] = i < n ? vals_in[i] : 0;
+    }
+#pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = base + k * 64 + lane;
         const bool valid = i < n;
-        int d = 0;
-        if (valid) {
-            kv[k] = keys_in[i];
-            vv[k] = vals_in[i];
-            d = digit_of(kv[k], shift);
-        }
+        const int d = valid ? digit_of(kv[k], shift, pb) : 0;
         unsigned long long m = __ballot(valid);
         for (int b = 0; b < 8; ++b) {
             const unsigned long long bb = __ballot(valid && ((d >> b) & 1));
@@ -223,15 +232,19 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restric
         }
     }
     __syncthreads();
+    int64_t pos[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k)  // the digits' tile offsets, all in flight
+        pos[k] = dg[k] < 0 ? -1 : offs[(int64_t)dg[k] * ntiles + blockIdx.x] + wcnt[wave][dg[k]] + rank[k];
+#pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         if (dg[k] < 0) continue;
-        const int64_t pos = offs[(int64_t)dg[k] * ntiles + blockIdx.x] + wcnt[wave][dg[k]] + rank[k];
-        if (pos < 0 || pos >= n) {
+        if (pos[k] < 0 || pos[k] >= n) {
             atomicOr(health, H_SCATTER);
             continue;
         }
-        keys_out[pos] = kv[k];
-        vals_out[pos] = vv[k];
+        keys_out[pos[k]] = kv[k];
+        vals_out[pos[k]] = vv[k];
     }
 }
 

@@ -2091,16 +2091,33 @@ __global__ void split_group_elems(const LabelInfo *__restrict__ label, const int
 }
 
 // Gradient from the expected-count records sorted by (arc, token position):
-// the first record of each arc sums its run in position order.
+// the first record of each arc sums its run in position order, reading eight
+// records ahead (the additions stay in order).
 __global__ void record_sums(const uint64_t *__restrict__ key, const float *__restrict__ val, int64_t n,
                             float *__restrict__ grad)
 {
+    constexpr int U = 8;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t arc = (uint32_t)(key[j] >> 32);
         if (key[j] == kRecSentinel) continue;  // unused record slots sort last
         if (j > 0 && (uint32_t)(key[j - 1] >> 32) == arc) continue;
         float s = 0.0f;
-        for (int64_t x = j; x < n && (uint32_t)(key[x] >> 32) == arc; ++x) s += val[x];
+        for (int64_t x = j;; x += U) {
+            uint32_t a[U];
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {  // the sentinel's arc part matches no arc
+                a[u] = x + u < n ? (uint32_t)(key[x + u] >> 32) : 0xffffffffu;
+                v[u] = x + u < n ? val[x + u] : 0.0f;
+            }
+            bool run = true;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                run = run && a[u] == arc;
+                if (run) s += v[u];
+            }
+            if (!run) break;
+        }
         grad[arc] = s;
     }
 }

@@ -771,12 +771,12 @@ int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, co
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(radix_hist<int32_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
-                           N, shift, ntiles, hist);
+                           N, shift, 0, ntiles, hist);
         ScanSource src;
         src.i64 = hist;
         TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
         hipLaunchKernelGGL(radix_scatter<int32_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
-                           (const int32_t *)v0, N, shift, ntiles, (const int64_t *)hist, k1, v1, f->health);
+                           (const int32_t *)v0, N, shift, 0, ntiles, (const int64_t *)hist, k1, v1, f->health);
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
@@ -832,22 +832,23 @@ int reduce_records(wfst_fst *f, hipStream_t s, int64_t n, int64_t N, uint64_t *k
     int64_t *hist, *tiles;
     TRY(ensure_t(f->ws[W_HIST], 256 * ntiles, s, &hist));
     TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(256 * ntiles), s, &tiles));
-    // 2^bits > every value, so the all-ones sentinel keys sort after all records
+    // keys arc:position sorted as (arc << pos_bits) | position, on its low
+    // pos_bits + arc_bits bits; 2^bits > every value, so the all-ones sentinel
+    // keys (all ones there too) sort after all records
     int pos_bits = 1, arc_bits = 1;
     while (pos_bits < 32 && ((int64_t)1 << pos_bits) <= N) ++pos_bits;
     while (arc_bits < 32 && ((int64_t)1 << arc_bits) <= f->A) ++arc_bits;
     std::vector<int> shifts;
-    for (int sh = 0; sh < pos_bits; sh += 8) shifts.push_back(sh);
-    for (int sh = 0; sh < arc_bits; sh += 8) shifts.push_back(32 + sh);
+    for (int sh = 0; sh < pos_bits + arc_bits; sh += 8) shifts.push_back(sh);
     int32_t *iv0 = reinterpret_cast<int32_t *>(v0), *iv1 = reinterpret_cast<int32_t *>(v1);
     for (int sh : shifts) {
         hipLaunchKernelGGL(radix_hist<uint64_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s,
-                           (const uint64_t *)k0, n, sh, ntiles, hist);
+                           (const uint64_t *)k0, n, sh, pos_bits, ntiles, hist);
         ScanSource src;
         src.i64 = hist;
         TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
         hipLaunchKernelGGL(radix_scatter<uint64_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s,
-                           (const uint64_t *)k0, (const int32_t *)iv0, n, sh, ntiles, (const int64_t *)hist, k1, iv1,
+                           (const uint64_t *)k0, (const int32_t *)iv0, n, sh, pos_bits, ntiles, (const int64_t *)hist, k1, iv1,
                            f->health);
         std::swap(k0, k1);
         std::swap(iv0, iv1);
