@@ -1266,10 +1266,10 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     __shared__ BwdStep s_win[kBwdWin];                                 // step metadata ring
     float *val0 = reinterpret_cast<float *>(smem);                     // [Q+1]
     float *val1 = val0 + (Q + 1);                                      // [Q+1]
-    int32_t *mark = reinterpret_cast<int32_t *>(val1 + (Q + 1));       // [Q+1] step stamp of states to compute
-    float *aval = reinterpret_cast<float *>(mark + (Q + 1));           // [Q+1] alpha~_{t-1} - c_{t-1} there
-    int2 *list = reinterpret_cast<int2 *>(aval + (Q + 1));             // [list_cap] {segment, key}
+    float *aval = val1 + (Q + 1);                                      // [Q+1] alpha~_{t-1} - c_{t-1} there
+    int2 *list = reinterpret_cast<int2 *>(smem + ((12 * (int64_t)(Q + 1) + 7) & ~(int64_t)7));  // [list_cap] {segment, key}
     double *lval = reinterpret_cast<double *>(list + list_cap);        // [list_cap] unnormalised value
+    uint16_t *mark = reinterpret_cast<uint16_t *>(lval + list_cap);    // [Q+1] step stamp of states to compute
     __shared__ int s_item, s_count;
     __shared__ unsigned long long s_cmax[3];
     __shared__ uint64_t s_rkey[kRecStage];
@@ -1322,7 +1322,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             const float f = q < Q ? final_score[q] : WFST_NINF;
             vT[q] = (t1 == T && f != WFST_NINF) ? f - fmax0 : WFST_NINF;
             vO[q] = WFST_NINF;
-            mark[q] = -1;
+            mark[q] = 0;  // no step's stamp
         }
         __syncthreads();
         double C;  // log scale: log beta_t = beta^_t + C_t
@@ -1404,21 +1404,28 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             float *cur = (t & 1) ? val0 : val1;   // beta~_{t-1}
             const int i = o0 + t - 1;
             // A: mark the states of step t-1 (with alpha~_{t-1} for the records),
-            // stage the slice headers of w_t
+            // stage the slice headers of w_t.  Stamps are 16-bit, (t - 1) % 65535 + 1:
+            // every step t divisible by 65535 first clears them all, so no stamp of a
+            // step 65535 or more later survives to look like this step's.
+            const uint16_t stamp = (uint16_t)((t - 1) % 65535 + 1);
+            if (t % 65535 == 0) {  // uniform (t is)
+                for (int q = tid; q <= Q; q += NT) mark[q] = 0;
+                __syncthreads();
+            }
             if (t >= 2) {
 #pragma unroll
                 for (int u = 0; u < TPF; ++u)
                     if (tk[u] >= 0) {
-                        mark[tk[u]] = t;
+                        mark[tk[u]] = stamp;
                         aval[tk[u]] = ta[u] - cm;
                     }
                 for (int j = tid + TPF * NT; j < lf_n; j += NT) {
                     const int q = fl.seg_key[lf_first + j];
-                    mark[q] = t;
+                    mark[q] = stamp;
                     aval[q] = rec ? ap[j] - cm : WFST_NINF;
                 }
             } else if (tid == 0) {
-                mark[start] = t;
+                mark[start] = stamp;
                 aval[start] = 0.0f;  // alpha~_0 = 0 at the start state, no normaliser
             }
             const float o = rec ? (float)((t >= 2 ? aC : 0.0) + C - lz) : 0.0f;  // C = log scale of beta_t
@@ -1431,7 +1438,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             uint32_t hits = 0;
 #pragma unroll
             for (int u = 0; u < RPF; ++u)
-                if (rk[u] >= 0 && mark[rk[u]] == t) hits |= 1u << u;
+                if (rk[u] >= 0 && mark[rk[u]] == stamp) hits |= 1u << u;
             if (stage) copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
             if (t < t1) {  // tape of beta^_t (this step's input), normalised at the end of step t+1
 #pragma unroll
@@ -1510,7 +1517,7 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
             }
             for (int j = tid + RPF * NT; j < li.n_segs; j += NT) {
                 const int key = rl.seg_key[li.seg_first + j];
-                if (mark[key] == t) {
+                if (mark[key] == stamp) {
                     const int pos = atomicAdd(&s_count, 1);
                     if (pos < list_cap) list[pos] = make_int2(j, key);
                 }

@@ -325,9 +325,11 @@ size_t lds_viterbi(const wfst_fst *f, bool gmem)
 }
 size_t lds_backward(const wfst_fst *f)
 {
+    // three FP32 vectors (8-byte aligned end), the segment list and its values,
+    // then the 16-bit step stamps
     const size_t q1 = (size_t)f->Q + 1;
-    return 3 * q1 * sizeof(float) + q1 * sizeof(int32_t) +
-           (size_t)backward_list_cap(f) * (sizeof(int2) + sizeof(double));
+    return ((3 * q1 * sizeof(float) + 7) & ~(size_t)7) +
+           (size_t)backward_list_cap(f) * (sizeof(int2) + sizeof(double)) + q1 * sizeof(uint16_t);
 }
 size_t lds_lse(const wfst_fst *f, const DevLayout &l)
 {
