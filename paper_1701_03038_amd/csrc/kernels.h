@@ -101,13 +101,16 @@ __device__ __forceinline__ const float *alpha_slot(const TapeView &tp, const Blo
 }
 
 // Expected-count records written by the backward pass: one per (arc, visit)
-// with a nonzero posterior, key = (arc << 32) | token position.  count may
-// pass cap: records beyond cap are dropped and the caller falls back.
+// with a nonzero posterior, key = (e << 32) | token position, where e is the
+// arc's slot in the reverse layout (one slot per arc; elem_arc maps it back).
+// count may pass cap: records beyond cap are dropped and the caller falls back.
 //
 // Alternatively (acc != null) each posterior is added at once to its arc's
-// fixed-point accumulator: acc[arc] += round(value * 2^S), an integer atomic,
-// so the sum does not depend on the order of the additions (no records, no
-// sort; used when records could not fit, or when asked for).
+// fixed-point accumulator, also indexed by reverse-layout slot: acc[e] +=
+// round(value * 2^S), an integer atomic, so the sum does not depend on the
+// order of the additions (no records, no sort; used when records could not
+// fit, or when asked for).  A step's additions then fall in its label's
+// slices instead of all over the arc ids.
 struct RecordSink {
     uint64_t *key = nullptr;  // null: no records
     float *val = nullptr;
@@ -115,7 +118,7 @@ struct RecordSink {
     unsigned long long *total = nullptr;  // records (independent of scheduling)
     int64_t cap = 0;
     const float *grad_log_z = nullptr;  // g_b (null = 1)
-    unsigned long long *acc = nullptr;  // [num_arcs] fixed-point sums (two's complement)
+    unsigned long long *acc = nullptr;  // [reverse slots] fixed-point sums (two's complement)
     const double *fx_scale = nullptr;   // device scalar 2^S
 };
 

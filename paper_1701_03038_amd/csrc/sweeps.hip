@@ -1557,13 +1557,13 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     const SliceInfo si{sv.x, sv.y, sv.z, sv.w};
                     for (int r0 = 0; r0 < si.height; r0 += RB) {
                         Elem e[RB];
-                        int32_t arc_of[RB];  // arc ids, for the posteriors (loaded with the rows)
+                        int32_t slot_of[RB];  // reverse-layout slots, for the posteriors
 #pragma unroll
                         for (int u = 0; u < RB; ++u) {  // no branches: all RB loads in flight together
                             const int pos = si.base + min(r0 + u, si.height - 1) * si.width + l;
                             const int32_t o = rl.other[pos];
                             const float sc = rl.score[pos];
-                            arc_of[u] = a != WFST_NINF ? rl.elem_arc[pos] : -1;
+                            slot_of[u] = pos;
                             e[u] = r0 + u < si.height ? Elem{o, sc} : Elem{Q, 0.0f};
                         }
                         float g[RB];
@@ -1586,15 +1586,14 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                                     // posteriors that round to 0 at the accumulators' scale add nothing
                                     const long long q = __double2ll_rn((double)v[u] * fx);
                                     if (q == 0) continue;
-                                    atomicAdd(&rs.acc[arc_of[u]], (unsigned long long)q);
+                                    atomicAdd(&rs.acc[slot_of[u]], (unsigned long long)q);
                                 }
                             } else if (nrec > 0) {
                                 int at = wave_append(nrec, &s_rn, lane);
 #pragma unroll
                                 for (int u = 0; u < RB; ++u) {
                                     if (v[u] == 0.0f) continue;
-                                    const int arc = arc_of[u];
-                                    const uint64_t key = ((uint64_t)(uint32_t)arc << 32) | (uint32_t)i;
+                                    const uint64_t key = ((uint64_t)(uint32_t)slot_of[u] << 32) | (uint32_t)i;
                                     if (at < kRecStage) {
                                         s_rkey[at] = key;
                                         s_rval[at] = v[u];
@@ -2097,35 +2096,37 @@ __global__ void split_group_elems(const LabelInfo *__restrict__ label, const int
     }
 }
 
-// Gradient from the expected-count records sorted by (arc, token position):
-// the first record of each arc sums its run in position order, reading eight
-// records ahead (the additions stay in order).
+// Gradient from the expected-count records sorted by (reverse slot, token
+// position): the first record of each slot sums its run in position order,
+// reading eight records ahead (the additions stay in order), and writes it to
+// the slot's arc.
 __global__ void record_sums(const uint64_t *__restrict__ key, const float *__restrict__ val, int64_t n,
-                            float *__restrict__ grad)
+                            const int32_t *__restrict__ elem_arc, float *__restrict__ grad)
 {
     constexpr int U = 8;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t arc = (uint32_t)(key[j] >> 32);
-        if (key[j] == kRecSentinel) continue;  // unused record slots sort last
-        if (j > 0 && (uint32_t)(key[j - 1] >> 32) == arc) continue;
+        const uint32_t slot = (uint32_t)(key[j] >> 32);
+        if (key[j] == kRecSentinel) continue;  // unused record entries (sentinels) sort last
+        if (j > 0 && (uint32_t)(key[j - 1] >> 32) == slot) continue;
         float s = 0.0f;
         for (int64_t x = j;; x += U) {
             uint32_t a[U];
             float v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {  // the sentinel's arc part matches no arc
+            for (int u = 0; u < U; ++u) {  // the sentinel's slot part matches no slot
                 a[u] = x + u < n ? (uint32_t)(key[x + u] >> 32) : 0xffffffffu;
                 v[u] = x + u < n ? val[x + u] : 0.0f;
             }
             bool run = true;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                run = run && a[u] == arc;
+                run = run && a[u] == slot;
                 if (run) s += v[u];
             }
             if (!run) break;
         }
-        grad[arc] = s;
+        const int32_t k = elem_arc[slot];
+        if (k >= 0) grad[k] = s;
     }
 }
 
@@ -2573,13 +2574,16 @@ __global__ void __launch_bounds__(256) fx_scale_kernel(const float *__restrict__
     }
 }
 
-// grad[k] = acc[k] / 2^S
-__global__ void fx_to_grad(const unsigned long long *__restrict__ acc, int64_t n, const double *__restrict__ scale,
-                           float *__restrict__ grad)
+// grad[elem_arc[e]] = acc[e] / 2^S over the reverse slots e (each arc has one
+// slot; padding slots have no arc)
+__global__ void fx_to_grad(const unsigned long long *__restrict__ acc, const int32_t *__restrict__ elem_arc, int64_t n,
+                           const double *__restrict__ scale, float *__restrict__ grad)
 {
     const double inv = 1.0 / *scale;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        grad[i] = (float)((double)(long long)acc[i] * inv);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = elem_arc[e];
+        if (k >= 0) grad[k] = (float)((double)(long long)acc[e] * inv);
+    }
 }
 
 // =====================================================================

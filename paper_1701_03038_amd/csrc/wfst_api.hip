@@ -834,12 +834,13 @@ int reduce_records(wfst_fst *f, hipStream_t s, int64_t n, int64_t N, uint64_t *k
     int64_t *hist, *tiles;
     TRY(ensure_t(f->ws[W_HIST], 256 * ntiles, s, &hist));
     TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(256 * ntiles), s, &tiles));
-    // keys arc:position sorted as (arc << pos_bits) | position, on its low
-    // pos_bits + arc_bits bits; 2^bits > every value, so the all-ones sentinel
-    // keys (all ones there too) sort after all records
+    // keys slot:position (slot: the arc's reverse-layout slot) sorted as
+    // (slot << pos_bits) | position, on its low pos_bits + arc_bits bits;
+    // 2^bits > every value, so the all-ones sentinel keys (all ones there too)
+    // sort after all records
     int pos_bits = 1, arc_bits = 1;
     while (pos_bits < 32 && ((int64_t)1 << pos_bits) <= N) ++pos_bits;
-    while (arc_bits < 32 && ((int64_t)1 << arc_bits) <= f->A) ++arc_bits;
+    while (arc_bits < 32 && ((int64_t)1 << arc_bits) <= f->rev.n_elem) ++arc_bits;
     std::vector<int> shifts;
     for (int sh = 0; sh < pos_bits + arc_bits; sh += 8) shifts.push_back(sh);
     int32_t *iv0 = reinterpret_cast<int32_t *>(v0), *iv1 = reinterpret_cast<int32_t *>(v1);
@@ -856,7 +857,7 @@ int reduce_records(wfst_fst *f, hipStream_t s, int64_t n, int64_t N, uint64_t *k
         std::swap(iv0, iv1);
     }
     hipLaunchKernelGGL(record_sums, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, (const uint64_t *)k0,
-                       (const float *)reinterpret_cast<float *>(iv0), n, grad);
+                       (const float *)reinterpret_cast<float *>(iv0), n, (const int32_t *)f->rev.elem_arc, grad);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -1643,17 +1644,19 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
         return WFST_OK;
     };
     // Fixed-point counts: each posterior is added to its arc's 64-bit integer
-    // accumulator during the backward sweep; one conversion pass writes the
-    // gradient.  Integer sums do not depend on the order of the additions.
+    // accumulator (indexed by the arc's reverse-layout slot) during the
+    // backward sweep; one conversion pass writes the gradient.  Integer sums do
+    // not depend on the order of the additions.
     auto fixed_point_counts = [&]() -> int {
         unsigned long long *acc;
         double *scale;
-        TRY(ensure_t(f->ws[W_FXACC], f->A, s, &acc));
+        const int64_t n_slots = f->rev.n_elem;
+        TRY(ensure_t(f->ws[W_FXACC], n_slots, s, &acc));
         TRY(ensure_t(f->ws[W_FXSCALE], 1, s, &scale));
         {
             ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
-            hipLaunchKernelGGL(fill_i64, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s,
-                               reinterpret_cast<int64_t *>(acc), f->A, (int64_t)0);
+            hipLaunchKernelGGL(fill_i64, dim3(grid_for(n_slots, 256, 8192)), dim3(256), 0, s,
+                               reinterpret_cast<int64_t *>(acc), n_slots, (int64_t)0);
         }
         hipLaunchKernelGGL(fx_scale_kernel, dim3(1), dim3(256), 0, s, grad_log_z, B, N, scale);
         hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)C_COUNT, 0);
@@ -1664,8 +1667,9 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
         TRY(backward_pass(rs));
         {
             ProfScope prof(f, s, WFST_KERNEL_COUNTS);
-            hipLaunchKernelGGL(fx_to_grad, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s,
-                               (const unsigned long long *)acc, f->A, (const double *)scale, grad_arc_score);
+            hipLaunchKernelGGL(fx_to_grad, dim3(grid_for(n_slots, 256, 8192)), dim3(256), 0, s,
+                               (const unsigned long long *)acc, (const int32_t *)f->rev.elem_arc, n_slots,
+                               (const double *)scale, grad_arc_score);
         }
         HIP_OK(hipGetLastError());
         return WFST_OK;
