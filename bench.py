@@ -62,7 +62,8 @@ def algorithmic_bytes(fst_dev, batch, Q=None):
       backward  8 A_a + 8 D'_a         (the same over the reverse layout)
       counts    16 A_a per label the batch reads ({src, dst, score} + gradient write)
       score update 24 per arc (two layouts: arc id, score gather, score write)
-      gradient fill 4 per arc.
+      gradient fill 4 per arc (on the record path the backward sweep does
+                    it, and its row then carries these bytes).
     With Q given (state vectors too large for on-chip memory) every pass also
     gathers 4 A_a and writes 4 D_a (4 D'_a) per symbol and the counts stream
     alpha and beta, 8 Q per visit."""
@@ -106,7 +107,9 @@ def kernel_table(prof, bytes_per, steps, traffic=None, fused_counts=False):
     A checkpointed backward pass is one launch per block of steps and comes
     with a second forward pass (the blocks' recompute); with fused_counts the
     expected counts are taken inside the backward sweep, whose row then
-    carries the count bytes too (the counts row is the conversion pass)."""
+    carries the count bytes too (the counts row is the conversion pass).
+    With no gradient-fill launches the backward sweep zero-filled the
+    gradient itself, and its row carries those bytes."""
     launches = {k: n for k, (ms, n) in prof.items()}
     blocks = max(1, round(launches.get("backward", 0) / max(steps, 1)))
     passes = {k: n / max(steps, 1) for k, n in launches.items()}
@@ -114,6 +117,9 @@ def kernel_table(prof, bytes_per, steps, traffic=None, fused_counts=False):
         passes["backward"] = 1
         passes["forward"] = 2
     by = dict(bytes_per)
+    if launches.get("grad_fill", 0) == 0 and launches.get("backward", 0) > 0 and "grad_fill" in by:
+        by["backward"] = by["backward"] + by["grad_fill"]
+        by["grad_fill"] = 0.0
     if fused_counts:
         by["backward"] = by["backward"] + by["counts"]
         by["counts"] = 0.0

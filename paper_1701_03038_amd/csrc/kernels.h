@@ -120,6 +120,10 @@ struct RecordSink {
     const float *grad_log_z = nullptr;  // g_b (null = 1)
     unsigned long long *acc = nullptr;  // [reverse slots] fixed-point sums (two's complement)
     const double *fx_scale = nullptr;   // device scalar 2^S
+    // The gradient the records are later summed into, zero-filled by the sweep
+    // itself, a slab per workgroup and step (null: the caller fills it).
+    float *fill = nullptr;
+    int64_t fill_n = 0;
 };
 
 // beta~ of token i: the full tape, or the block buffer of the token's block

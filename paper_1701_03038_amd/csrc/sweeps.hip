@@ -1185,6 +1185,24 @@ constexpr int kRecStage = 64;
 constexpr int kRecChunk = 256;
 static_assert(kRecStage <= kRecChunk, "one step's staged records fit a chunk");
 constexpr uint64_t kRecSentinel = ~0ull;
+// Zero-fill of the gradient inside the sweep: workgroup w writes slabs w,
+// w + G, w + 2G, ... (G workgroups) of 8 floats per thread, one slab at the
+// end of each step (stores issued after the step's loads, so no load waits on
+// them), the rest when its queue is empty.  rs.fill is 16-byte aligned;
+// streaming stores, so that the fill does not evict layout lines from L2.
+constexpr int kFillPerThread = 8;
+__device__ __forceinline__ void fill_gradient_slab(const RecordSink &rs, int64_t slab_first, int tid)
+{
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const int64_t x = slab_first + kFillPerThread * (int64_t)tid;
+    if (x + kFillPerThread <= rs.fill_n) {
+        v4f *q = reinterpret_cast<v4f *>(rs.fill + x);
+        __builtin_nontemporal_store((v4f){0.0f, 0.0f, 0.0f, 0.0f}, q);
+        __builtin_nontemporal_store((v4f){0.0f, 0.0f, 0.0f, 0.0f}, q + 1);
+    } else {
+        for (int64_t y = x; y < rs.fill_n; ++y) __builtin_nontemporal_store(0.0f, rs.fill + y);
+    }
+}
 
 // The step table of a backward launch: entry i describes the step of token i
 // (step t = i - o0 + 1 of its sentence).  Built in parallel over the tokens
@@ -1284,6 +1302,9 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
     const __amdgpu_buffer_rsrc_t slice_rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)rl.slice, (short)0, (int)min<int64_t>(rl.n_slice * (int64_t)sizeof(SliceInfo), INT32_MAX), 0x00020000);
     const double fx = rs.acc ? *rs.fx_scale : 0.0;  // fixed-point scale of the accumulators
+    const int64_t fill_slab = (int64_t)kFillPerThread * NT;  // floats per gradient slab (rs.fill)
+    int64_t fill_at = (int64_t)blockIdx.x * fill_slab;       // next slab of this workgroup
+    const int64_t fill_stride = (int64_t)gridDim.x * fill_slab;
     if (tid == 0) {
         s_rn = 0;
         s_cbase = 0;
@@ -1656,6 +1677,10 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
                     if (tk_prev[u] >= 0) prev[tk_prev[u]] = WFST_NINF;
                 for (int j = tid + TPF * NT; j < lfp_n; j += NT) prev[fl.seg_key[lfp_first + j]] = WFST_NINF;
             }
+            if (rs.fill && fill_at < rs.fill_n) {  // this workgroup's next gradient slab
+                fill_gradient_slab(rs, fill_at, tid);
+                fill_at += fill_stride;
+            }
             if (t >= 2 && tid == 0) {
                 tp.b_max[i - 1] = 0.0f;  // the tape is normalised
                 tp.b_log[i - 1] = C;
@@ -1691,9 +1716,11 @@ backward_sweep(DevLayout fl, DevLayout rl, int32_t Q, int32_t start,
         }
         __syncthreads();
     }
-    // the records staged by the last step, the unused tail of the last chunk,
-    // and the workgroup's record count
+    // the rest of the gradient fill; the records staged by the last step, the
+    // unused tail of the last chunk, and the workgroup's record count
     __syncthreads();
+    if (rs.fill)
+        for (; fill_at < rs.fill_n; fill_at += fill_stride) fill_gradient_slab(rs, fill_at, tid);
     if (rs.key != nullptr) {
         copy_staged_records(rs, s_rkey, s_rval, s_rflush, s_fbase, s_tailn, s_tailb, tid, NT);
         for (int x = s_cused + tid; x < s_csize; x += NT) {

@@ -1590,7 +1590,11 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
     // (a graph takes fixed-point counts where the records would need a read-back)
     const bool fx = f->A > 0 && B > 0 && N > 0 &&
                     (f->fx_counts || backward_in_gmem(f) || (f->graph_mode && !f->rec_off));
-    if (f->A > 0 && !fx) {
+    // on the record path the backward sweep zero-fills the gradient itself
+    // (bandwidth it leaves unused); else one fill kernel first
+    const bool fill_in_sweep = f->A > 0 && !fx && !f->rec_off && B > 0 && N > 0 &&
+                               ((uintptr_t)grad_arc_score & 15) == 0;
+    if (f->A > 0 && !fx && !fill_in_sweep) {
         ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
         hipLaunchKernelGGL(fill_f32, dim3(grid_for(f->A, 256, 8192)), dim3(256), 0, s, grad_arc_score, f->A, 0.0f);
     }
@@ -1638,7 +1642,9 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
             DISPATCH_NT(r, f->nt, launch_forward, f, s, bv, tp, bk, nullptr)
             if (r != WFST_OK) return r;
             hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, counters + C_QUEUE, (int64_t)1, 0);
-            DISPATCH_NT(r, f->nt, launch_backward, f, s, bv, tp, bk, sink)
+            RecordSink sk = sink;
+            if (k != K - 1) sk.fill = nullptr;  // the first launch zero-fills the gradient
+            DISPATCH_NT(r, f->nt, launch_backward, f, s, bv, tp, bk, sk)
             if (r != WFST_OK) return r;
         }
         return WFST_OK;
@@ -1681,6 +1687,10 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
         rs.count = reinterpret_cast<unsigned long long *>(counters + C_RECS);
         rs.total = reinterpret_cast<unsigned long long *>(counters + C_RTOTAL);
         rs.grad_log_z = grad_log_z;
+        if (fill_in_sweep) {
+            rs.fill = grad_arc_score;
+            rs.fill_n = f->A;
+        }
         int64_t cap = std::min(kRecordsMax, f->rec_cap > 0 ? f->rec_cap : 16 * N + 4096);
         for (int attempt = 0; attempt < 2; ++attempt) {
             TRY(ensure_t(f->ws[W_RKEY0], cap, s, &rs.key));
