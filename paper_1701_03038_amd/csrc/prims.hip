@@ -141,9 +141,7 @@ __global__ void __launch_bounds__(1024) order_by_length(const int32_t *__restric
 
 // ---------------------------------------------------------------------
 // Stable LSD radix sort of (key, value) pairs (int32 or uint64 keys, int32
-// values), 8 bits per pass.  A uint64 key hi:lo with lo < 2^pb is sorted as
-// the packed value (hi << pb) | lo, so that hi and lo need only their own
-// significant bits between them (pb = 32: the key as it is).
+// values), 8 bits per pass.
 // Tile = 1024 elements per block of 256 threads; each wavefront scatters a
 // contiguous quarter of it.
 // ---------------------------------------------------------------------
@@ -151,17 +149,13 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
-__device__ __forceinline__ int digit_of(int32_t key, int shift, int) { return ((uint32_t)key >> shift) & 0xff; }
-__device__ __forceinline__ int digit_of(uint64_t key, int shift, int pb)
-{
-    const uint64_t packed = ((key >> 32) << pb) | (key & 0xffffffffull);
-    return (int)((packed >> shift) & 0xff);
-}
+__device__ __forceinline__ int digit_of(int32_t key, int shift) { return ((uint32_t)key >> shift) & 0xff; }
+__device__ __forceinline__ int digit_of(uint64_t key, int shift) { return (int)((key >> shift) & 0xff); }
 
 // hist[d * ntiles + tile] = occurrences of digit d in the tile
 template <class K>
 __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__ keys, int64_t n, int shift,
-                                                           int pb, int64_t ntiles, int64_t *__restrict__ hist)
+                                                           int64_t ntiles, int64_t *__restrict__ hist)
 {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
@@ -169,7 +163,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = base + (int64_t)k * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[digit_of(keys[i], shift, pb)], 1);
+        if (i < n) atomicAdd(&h[digit_of(keys[i], shift)], 1);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -182,7 +176,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist(const K *__restrict__
 template <class K>
 __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restrict__ keys_in,
                                                               const int32_t *__restrict__ vals_in, int64_t n,
-                                                              int shift, int pb, int64_t ntiles,
+                                                              int shift, int64_t ntiles,
                                                               const int64_t *__restrict__ offs,
                                                               K *__restrict__ keys_out,
                                                               int32_t *__restrict__ vals_out,
@@ -208,7 +202,7 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const K *__restric
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t i = base + k * 64 + lane;
         const bool valid = i < n;
-        const int d = valid ? digit_of(kv[k], shift, pb) : 0;
+        const int d = valid ? digit_of(kv[k], shift) : 0;
         unsigned long long m = __ballot(valid);
         for (int b = 0; b < 8; ++b) {
             const unsigned long long bb = __ballot(valid && ((d >> b) & 1));

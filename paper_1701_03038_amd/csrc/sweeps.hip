@@ -2123,37 +2123,83 @@ __global__ void split_group_elems(const LabelInfo *__restrict__ label, const int
     }
 }
 
-// Gradient from the expected-count records sorted by (reverse slot, token
-// position): the first record of each slot sums its run in position order,
-// reading eight records ahead (the additions stay in order), and writes it to
-// the slot's arc.
-__global__ void record_sums(const uint64_t *__restrict__ key, const float *__restrict__ val, int64_t n,
-                            const int32_t *__restrict__ elem_arc, float *__restrict__ grad)
+// Gradient from the expected-count records grouped by reverse slot (sorted),
+// summed per slot as 64-bit integers round(value * 2^S) (2^S from
+// fx_scale_kernel: no sum can overflow, and integer sums do not depend on the
+// order of the additions).  record_tiles: one wavefront per tile of 64
+// records sums every run piece in the tile by a segmented scan over the
+// lanes; a run that begins and ends inside the tile is written at once, the
+// pieces that cross a tile edge are kept in its RecTile.  record_runs: the
+// tile where such a run begins adds the tiles it spans and writes it.
+struct RecTile {
+    long long head;      // sum of the tile's first piece when its run began in an earlier tile (else 0)
+    long long tail;      // sum of the tile's last piece when its run begins here and goes on (else 0)
+    uint32_t tail_slot;  // slot of that run (0xffffffff: none)
+    int32_t full;        // 1: the tile is one piece of a run that began earlier and goes on
+};
+constexpr uint32_t kNoSlot = 0xffffffffu;  // the slot part of the sentinel keys
+
+__global__ void record_tiles(const uint64_t *__restrict__ key, const float *__restrict__ val, int64_t n,
+                             const int32_t *__restrict__ elem_arc, const double *__restrict__ scale,
+                             float *__restrict__ grad, RecTile *__restrict__ tiles, int64_t ntiles)
 {
-    constexpr int U = 8;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t slot = (uint32_t)(key[j] >> 32);
-        if (key[j] == kRecSentinel) continue;  // unused record entries (sentinels) sort last
-        if (j > 0 && (uint32_t)(key[j - 1] >> 32) == slot) continue;
-        float s = 0.0f;
-        for (int64_t x = j;; x += U) {
-            uint32_t a[U];
-            float v[U];
+    const int lane = threadIdx.x & 63;
+    const double sc = *scale, inv = 1.0 / sc;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t tile = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; tile < ntiles; tile += nw) {
+        const int64_t j = tile * 64 + lane;
+        const uint64_t k = j < n ? key[j] : kRecSentinel;
+        const uint32_t slot = (uint32_t)(k >> 32);
+        long long q = k != kRecSentinel ? __double2ll_rn((double)val[j] * sc) : 0;
+        const uint32_t before = tile > 0 ? (uint32_t)(key[tile * 64 - 1] >> 32) : kNoSlot;
+        const uint32_t after = (tile + 1) * 64 < n ? (uint32_t)(key[(tile + 1) * 64] >> 32) : kNoSlot;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {  // the sentinel's slot part matches no slot
-                a[u] = x + u < n ? (uint32_t)(key[x + u] >> 32) : 0xffffffffu;
-                v[u] = x + u < n ? val[x + u] : 0.0f;
-            }
-            bool run = true;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                run = run && a[u] == slot;
-                if (run) s += v[u];
-            }
-            if (!run) break;
+        for (int o = 1; o < 64; o <<= 1) {  // inclusive scan within runs (a run's lanes are contiguous)
+            const long long qo = __shfl_up(q, o, 64);
+            const uint32_t so = __shfl_up(slot, o, 64);
+            if (lane >= o && so == slot) q += qo;
         }
-        const int32_t k = elem_arc[slot];
-        if (k >= 0) grad[k] = s;
+        const uint32_t slot0 = __shfl(slot, 0, 64), slot63 = __shfl(slot, 63, 64);
+        const uint32_t next = __shfl_down(slot, 1, 64);
+        const bool last = lane == 63 || next != slot;  // last lane of its piece
+        const bool from_before = slot == slot0 && before == slot;
+        const bool to_after = lane == 63 && after == slot;
+        if (last && slot != kNoSlot && !from_before && !to_after) {  // a whole run inside the tile
+            const int32_t a = elem_arc[slot];
+            if (a >= 0) grad[a] = (float)((double)q * inv);
+        }
+        const uint64_t other = __ballot(slot != slot0);
+        const int l0 = other ? __builtin_ctzll(other) - 1 : 63;  // last lane of the first piece
+        const bool head = slot0 != kNoSlot && before == slot0;
+        const long long head_sum = __shfl(q, l0, 64), tail_sum = __shfl(q, 63, 64);
+        const bool full = head && l0 == 63 && after == slot0;
+        const bool owner = slot63 != kNoSlot && after == slot63 && !(head && l0 == 63);
+        if (lane == 0) {
+            RecTile rt;
+            rt.head = head ? head_sum : 0;
+            rt.tail = owner ? tail_sum : 0;
+            rt.tail_slot = owner ? slot63 : kNoSlot;
+            rt.full = full ? 1 : 0;
+            tiles[tile] = rt;
+        }
+    }
+}
+
+__global__ void record_runs(const RecTile *__restrict__ tiles, int64_t ntiles, const int32_t *__restrict__ elem_arc,
+                            const double *__restrict__ scale, float *__restrict__ grad)
+{
+    const double inv = 1.0 / *scale;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+        const RecTile rt = tiles[t];
+        if (rt.tail_slot == kNoSlot) continue;
+        long long sum = rt.tail;
+        for (int64_t u = t + 1; u < ntiles; ++u) {  // the tiles the run spans, up to the one where it ends
+            const RecTile ru = tiles[u];
+            sum += ru.head;
+            if (!ru.full) break;
+        }
+        const int32_t a = elem_arc[rt.tail_slot];
+        if (a >= 0) grad[a] = (float)((double)sum * inv);
     }
 }
 

@@ -96,7 +96,7 @@ enum WsSlot {
     W_KEY0, W_KEY1, W_VAL0, W_VAL1, W_HIST, W_GRPLO, W_GRPN, W_NIP, W_ITEMBASE, W_ITEMS, W_ITEMSLOT,
     W_PARTIAL, W_SPLITE, W_SEOFF, W_VINFO, W_FROWS, W_FSUM, W_ABUF0, W_ABUF1, W_BBUF0, W_BBUF1,
     W_ILIST, W_ILOFF, W_RKEY0, W_RKEY1, W_RVAL0, W_RVAL1, W_GSCRATCH, W_FXACC, W_FXSCALE, W_EMSUM, W_SCAN0,
-    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_TVEC, W_TPMAX, W_TPZ, W_TPART, W_TBAR, W_LATFAR, W_TWORK, W_NUM
+    W_SCAN1, W_LATNODE, W_LATSCALE, W_BSTEP, W_TVEC, W_TPMAX, W_TPZ, W_TPART, W_TBAR, W_LATFAR, W_TWORK, W_RTILE, W_NUM
 };
 
 // Global memory for the per-workgroup state of sweeps whose state vectors do
@@ -773,12 +773,12 @@ int sort_visits(wfst_fst *f, hipStream_t s, int64_t N, const int32_t *tokens, co
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(radix_hist<int32_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
-                           N, shift, 0, ntiles, hist);
+                           N, shift, ntiles, hist);
         ScanSource src;
         src.i64 = hist;
         TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
         hipLaunchKernelGGL(radix_scatter<int32_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, (const int32_t *)k0,
-                           (const int32_t *)v0, N, shift, 0, ntiles, (const int64_t *)hist, k1, v1, f->health);
+                           (const int32_t *)v0, N, shift, ntiles, (const int64_t *)hist, k1, v1, f->health);
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
@@ -824,40 +824,48 @@ int final_posteriors(wfst_fst *f, const wfst_tape *tape, const float *grad_log_z
     return WFST_OK;
 }
 
-// Sort n expected-count records by (arc, token position) and sum each arc's
-// run into grad (arcs without records keep the zero fill).
+// Group n expected-count records by reverse-layout slot (radix sort on the
+// slot part of the keys slot:position) and sum each slot's run into its arc's
+// gradient as 64-bit fixed-point integers, whose sum does not depend on the
+// order of the run (arcs without records keep the zero fill).
 int reduce_records(wfst_fst *f, hipStream_t s, int64_t n, int64_t N, uint64_t *k0, float *v0, uint64_t *k1,
-                   float *v1, float *grad)
+                   float *v1, float *grad, const float *grad_log_z, int32_t B)
 {
     if (n == 0) return WFST_OK;
     const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     int64_t *hist, *tiles;
+    double *scale;
     TRY(ensure_t(f->ws[W_HIST], 256 * ntiles, s, &hist));
     TRY(ensure_t(f->ws[W_TILES], scan_tiles_for(256 * ntiles), s, &tiles));
-    // keys slot:position (slot: the arc's reverse-layout slot) sorted as
-    // (slot << pos_bits) | position, on its low pos_bits + arc_bits bits;
-    // 2^bits > every value, so the all-ones sentinel keys (all ones there too)
-    // sort after all records
-    int pos_bits = 1, arc_bits = 1;
-    while (pos_bits < 32 && ((int64_t)1 << pos_bits) <= N) ++pos_bits;
+    TRY(ensure_t(f->ws[W_FXSCALE], 1, s, &scale));
+    hipLaunchKernelGGL(fx_scale_kernel, dim3(1), dim3(256), 0, s, grad_log_z, B, N, scale);
+    // digits from the slot part (bits 32 and up) on its significant bits;
+    // 2^arc_bits > every slot, so the all-ones sentinel keys sort after all records
+    int arc_bits = 1;
     while (arc_bits < 32 && ((int64_t)1 << arc_bits) <= f->rev.n_elem) ++arc_bits;
     std::vector<int> shifts;
-    for (int sh = 0; sh < pos_bits + arc_bits; sh += 8) shifts.push_back(sh);
+    for (int sh = 0; sh < arc_bits; sh += 8) shifts.push_back(32 + sh);
     int32_t *iv0 = reinterpret_cast<int32_t *>(v0), *iv1 = reinterpret_cast<int32_t *>(v1);
     for (int sh : shifts) {
         hipLaunchKernelGGL(radix_hist<uint64_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s,
-                           (const uint64_t *)k0, n, sh, pos_bits, ntiles, hist);
+                           (const uint64_t *)k0, n, sh, ntiles, hist);
         ScanSource src;
         src.i64 = hist;
         TRY(launch_scan<int64_t>(s, src, 256 * ntiles, tiles, hist, nullptr));
         hipLaunchKernelGGL(radix_scatter<uint64_t>, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s,
-                           (const uint64_t *)k0, (const int32_t *)iv0, n, sh, pos_bits, ntiles, (const int64_t *)hist, k1, iv1,
+                           (const uint64_t *)k0, (const int32_t *)iv0, n, sh, ntiles, (const int64_t *)hist, k1, iv1,
                            f->health);
         std::swap(k0, k1);
         std::swap(iv0, iv1);
     }
-    hipLaunchKernelGGL(record_sums, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, (const uint64_t *)k0,
-                       (const float *)reinterpret_cast<float *>(iv0), n, (const int32_t *)f->rev.elem_arc, grad);
+    const int64_t nrt = (n + 63) / 64;  // tiles of 64 sorted records
+    RecTile *rt;
+    TRY(ensure_t(f->ws[W_RTILE], nrt, s, &rt));
+    hipLaunchKernelGGL(record_tiles, dim3(grid_for(nrt * 64, 256, 16384)), dim3(256), 0, s, (const uint64_t *)k0,
+                       (const float *)reinterpret_cast<float *>(iv0), n, (const int32_t *)f->rev.elem_arc,
+                       (const double *)scale, grad, rt, nrt);
+    hipLaunchKernelGGL(record_runs, dim3(grid_for(nrt, 256, 16384)), dim3(256), 0, s, (const RecTile *)rt, nrt,
+                       (const int32_t *)f->rev.elem_arc, (const double *)scale, grad);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
@@ -1712,7 +1720,7 @@ int wfst_backward(const wfst_fst *fc, const wfst_tape *tape, const float *grad_l
                 float *v1;
                 TRY(ensure_t(f->ws[W_RKEY1], std::max<int64_t>((int64_t)got[0], 1), s, &k1));
                 TRY(ensure_t(f->ws[W_RVAL1], std::max<int64_t>((int64_t)got[0], 1), s, &v1));
-                return reduce_records(f, s, (int64_t)got[0], N, rs.key, rs.val, k1, v1, grad_arc_score);
+                return reduce_records(f, s, (int64_t)got[0], N, rs.key, rs.val, k1, v1, grad_arc_score, grad_log_z, B);
             }
             // slots overflowed: grow to a bound no schedule can pass and run again.  A
             // chunk holds kRecChunk slots and is left with a tail under kRecStage;
