@@ -300,6 +300,8 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
     VPart *part = reinterpret_cast<VPart *>(smem + viterbi_state_bytes<GMEM>(Q));
     __shared__ int s_item;
     __shared__ unsigned long long s_best[NW];
+    constexpr int kBtChunk = 256;          // backtrace steps per LDS load of their offsets
+    __shared__ int64_t s_toff[kBtChunk];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -459,19 +461,28 @@ viterbi_sweep(DevLayout fl, int32_t Q, int32_t start, const float *__restrict__ 
             __syncthreads();
             continue;
         }
+        // backtrace (serial, on device: paper section 5.1), kBtChunk steps at a
+        // time: the steps' back-pointer offsets are first loaded into LDS by all
+        // threads, so that thread 0's chain waits on one load per step
+        int j = 0;
         if (tid == 0) {
             bv.status[b] = WFST_STATUS_OK;
             best_score[b] = unord_f32((uint32_t)(best >> 32));
-            // backtrace (serial, on device: paper section 5.1)
             const int qT = (int)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
-            int j = T > 0 ? (int)fin_idx[qT] : 0;
-            for (int t = T; t >= 1; --t) {
-                const int2 e = bp[bv.tok_off[o0 + t - 1] + j];
-                path_tmp[o0 + t - 1] = e.x;
-                j = e.y;
-            }
+            j = T > 0 ? (int)fin_idx[qT] : 0;
         }
-        __syncthreads();
+        for (int hi = T; hi >= 1; hi -= kBtChunk) {
+            const int lo = max(1, hi - kBtChunk + 1);
+            for (int t = lo + tid; t <= hi; t += NT) s_toff[t - lo] = bv.tok_off[o0 + t - 1];
+            __syncthreads();
+            if (tid == 0)
+                for (int t = hi; t >= lo; --t) {
+                    const int2 e = bp[s_toff[t - lo] + j];
+                    path_tmp[o0 + t - 1] = e.x;
+                    j = e.y;
+                }
+            __syncthreads();
+        }
         for (int i = o0 + tid; i < o1; i += NT) {
             const int arc = fl.elem_arc[path_tmp[i]];
             best_arcs[i] = arc;
