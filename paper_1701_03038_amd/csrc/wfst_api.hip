@@ -657,17 +657,26 @@ int launch_backward(const wfst_fst *fc, hipStream_t s, const BatchView &bv, cons
         return set_err(WFST_EUNSUPPORTED, "count records need the on-chip backward sweep");
     BwdStep *steps = nullptr;
     TRY(ensure_t(f->ws[W_BSTEP], std::max<int64_t>(bv.N, 1), s, &steps));
+    // the sweep zero-fills the gradient only when its grid covers the device
+    // (the grid is at most one workgroup per sentence); else one fill kernel
+    RecordSink sink = rs;
+    if (sink.fill && sh.grid < 2 * f->cu_count) {
+        ProfScope prof(f, s, WFST_KERNEL_GRAD_FILL);
+        hipLaunchKernelGGL(fill_f32, dim3(grid_for(sink.fill_n, 256, 8192)), dim3(256), 0, s, sink.fill, sink.fill_n,
+                           0.0f);
+        sink.fill = nullptr;
+    }
     ProfScope prof(f, s, WFST_KERNEL_BACKWARD);
     hipLaunchKernelGGL(bwd_step_table, dim3(grid_for(bv.B, 1)), dim3(64), 0, s, f->fwd, f->rev, bv, tp, bk,
                        (int32_t)(rs.key != nullptr || rs.acc != nullptr), steps);
     if (sh.gmem)
         hipLaunchKernelGGL((backward_sweep<NT, true>), dim3(sh.grid), dim3(NT), 0, s, f->fwd, f->rev, f->Q,
                            f->start, (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
-                           backward_list_cap(f), rs, (const BwdStep *)steps, sh.scratch, sh.slot);
+                           backward_list_cap(f), sink, (const BwdStep *)steps, sh.scratch, sh.slot);
     else
         hipLaunchKernelGGL((backward_sweep<NT, false>), dim3(sh.grid), dim3(NT), sh.lds, s, f->fwd, f->rev, f->Q,
                            f->start, (const float *)f->final_score, (const float *)f->final_max, bv, tp, bk,
-                           backward_list_cap(f), rs, (const BwdStep *)steps, nullptr, (int64_t)0);
+                           backward_list_cap(f), sink, (const BwdStep *)steps, nullptr, (int64_t)0);
     HIP_OK(hipGetLastError());
     return WFST_OK;
 }
