@@ -80,8 +80,9 @@ typedef struct wfst_options {
                                    fall back to per-workgroup slots).  A barrier wait is bounded: on a
                                    timeout the team stops and wfst_fst_health reports bit 64. */
     int64_t tape_budget_bytes;  /* auto mode checkpoints when the full tape exceeds this; 0 = 8 GiB */
-    int64_t count_records;      /* expected counts: 0 = auto (per-visit records of the backward pass, sorted
-                                   and summed per arc, while they fit; else the label-grouped count kernel
+    int64_t count_records;      /* expected counts: 0 = auto (per-visit records of the backward pass, grouped
+                                   by arc and summed as 64-bit integers of scale 2^S as below (the same
+                                   bits as -2), while they fit; else the label-grouped count kernel
                                    when its state fits LDS, else fixed-point accumulation),
                                    -1 = always the grouped count kernel,
                                    -2 = always fixed-point accumulation (each posterior added to its arc
@@ -246,9 +247,12 @@ int wfst_forward(const wfst_fst *fst, int32_t batch, int64_t num_tokens, const i
  *     sum_b g_b * E_b[number of uses of arc k] = d(sum_b g_b log Z_b)/d score_k.
  *   grad_final: DEVICE float[num_states] or NULL, overwritten with
  *     sum_b g_b * P_b(path ends in q).
- * Sentences without a path (or with a bad token) contribute zero.  The sum
- * over b and over visits is taken in a fixed order: results are bitwise
- * reproducible for a given FST, batch and library configuration.
+ * Sentences without a path (or with a bad token) contribute zero.  The sums
+ * over b and over visits are taken in a fixed order, or (per-visit records,
+ * fixed-point accumulation) as 64-bit integers whose sum does not depend on
+ * the order: results are bitwise reproducible for a given FST, batch and
+ * library configuration, and the records give the same bits as fixed-point
+ * accumulation.
  * Returns WFST_EINVAL when the FST's scores were replaced (set_scores) after
  * the forward pass that made the tape: the counts would pair the old alpha
  * with the new scores.
@@ -418,8 +422,7 @@ int wfst_em_update(wfst_fst *fst, const float *counts, float smoothing, const fl
  * the bound input buffers hold at that time (same batch and token counts),
  * bit for bit, except that counts the eager call would take from per-visit
  * records are taken in fixed point (equal to an eager call with
- * count_records = -2 bit for bit, and to the records within the posterior
- * accuracy).  The graph has its own
+ * count_records = -2 bit for bit, and so to the records).  The graph has its own
  * workspace and tape buffers, so eager calls on the FST between replays are
  * allowed (on the same stream).  Inside a graph nothing is read back to the
  * host, so:

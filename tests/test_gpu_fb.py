@@ -266,10 +266,12 @@ def test_checkpointing(wf, case):
 @pytest.mark.parametrize("case", ["tiny", "trigram"])
 def test_count_paths(wf, case):
     """Expected counts by per-visit records (default), by the label-grouped
-    count kernel (count_records=-1), and by the grouped kernel after a record
-    overflow (capacity 1): all within the oracle tolerance; records give the
-    same bits with and without checkpointing; the overflow fallback gives the
-    grouped kernel's bits."""
+    count kernel (count_records=-1), by the grouped kernel after a record
+    overflow (capacity 1) and by fixed-point accumulation (count_records=-2):
+    all within the oracle tolerance; records give the same bits with and
+    without checkpointing, and the same bits as fixed-point accumulation (each
+    run of records is summed as the same 64-bit integers round(v 2^S)); the
+    overflow fallback gives the grouped kernel's bits."""
     if case == "tiny":
         fst = synth.tiny_random_fst(11, 6, 3, 30, final_prob=0.7)
         batch = synth.random_batch(11, fst.num_ilabels, np.random.default_rng(11).integers(0, 30, 80))
@@ -280,7 +282,7 @@ def test_count_paths(wf, case):
     n_k = visits_per_arc(fst, batch)
     got = {}
     for ck in (2, 1):
-        for rec in (0, -1, 1):
+        for rec in (0, -1, 1, -2):
             d = wf.Fst.from_synth(fst, checkpoint=ck, count_records=rec)
             r = _fb_all(wf, d, batch)
             r2 = _fb_all(wf, d, batch)
@@ -291,6 +293,8 @@ def test_count_paths(wf, case):
     assert got[(2, 0)].tobytes() == got[(1, 0)].tobytes(), "records differ with checkpointing"
     assert got[(2, 1)].tobytes() == got[(2, -1)].tobytes(), "overflow fallback differs from the grouped kernel"
     assert got[(1, 1)].tobytes() == got[(1, -1)].tobytes()
+    for ck in (2, 1):
+        assert got[(ck, 0)].tobytes() == got[(ck, -2)].tobytes(), f"records differ from fixed point, ck={ck}"
 
 
 @pytest.mark.slow
